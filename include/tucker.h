@@ -1,0 +1,216 @@
+/*
+ * tucker.h -- C-ABI of the MI355X (gfx950) ST-HOSVD library.
+ *
+ * The library computes the sequentially truncated HOSVD of a dense N-way
+ * tensor (Austin, Ballard, Kolda, "Parallel Tensor Compression for
+ * Large-Scale Scientific Data", Alg. 1) and the Tucker reconstruction
+ * (Sec. II-C) on one GPU, with hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  A tensor of dims (I_1..I_N) is stored densely with mode 1 fastest:
+ *   element (i_1..i_N) sits at offset sum_k i_k prod_{m<k} I_m
+ * (the mode-1 unfolding is column-major, Sec. IV-A).  tk_shape.dims[0] is the
+ * fastest mode; modes are 0-based in this ABI.  The mode-n unfolding is never
+ * formed: kernels read the tensor as [B][J_n][L] with L = prod_{m<n} J_m and
+ * B = prod_{m>n} J_m, the block-column view of Sec. IV-C.
+ * Matrices (factors U_n, TTM operands, Gram matrices) are column-major with
+ * leading dimension equal to their row count, FP64 unless stated.
+ *
+ * Memory.  Every pointer named *_dev is a device pointer (hipMalloc memory or
+ * a torch CUDA tensor's data pointer) owned by the caller; the library never
+ * allocates or frees device memory.  Scratch memory comes in through a
+ * caller-owned workspace (ws, ws_bytes) whose minimum size the matching
+ * *_workspace_bytes query returns; ws must be 256-byte aligned.  Host
+ * pointers are plain host memory.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Work is enqueued on it.  gram_mode_n, ttm_mode_n and
+ * tucker_reconstruct are asynchronous: outputs are valid once the stream has
+ * been synchronised.  sthosvd_compress synchronises the stream before it
+ * returns, because rank-dependent sizes must reach the host.
+ *
+ * Errors.  Every call returns TK_OK (0) or a negative tk_status.  Arguments
+ * are validated on the host before any HIP call, so argument errors are
+ * reported without touching the device and leave outputs untouched.
+ * tk_last_error() returns a thread-local message for the last failure.
+ * A HIP runtime failure returns TK_ERR_HIP; a kernel-detected problem
+ * (non-finite input, eigensolver failure) is reported by the call that reads
+ * it back.
+ *
+ * Threading.  Calls are re-entrant as long as concurrent calls use distinct
+ * workspaces and outputs.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_MAX_NDIM 8
+/* Largest mode extent a Gram / eigensolve supports (the paper's working
+ * assumption is I_n <= 2000 with small I_n; this library supports <= 512). */
+#define TK_MAX_MODE_DIM 512
+
+typedef enum tk_status {
+    TK_OK = 0,
+    TK_ERR_INVALID_ARG = -1,     /* null pointer, bad shape, bad mode, eps < 0 or NaN ... */
+    TK_ERR_UNSUPPORTED = -2,     /* dtype x precision combination not provided */
+    TK_ERR_WORKSPACE = -3,       /* ws too small or misaligned */
+    TK_ERR_HIP = -4,             /* a HIP runtime call failed (message has the HIP error) */
+    TK_ERR_NONFINITE = -5,       /* the input holds Inf or NaN */
+    TK_ERR_EIG_NO_CONVERGENCE = -6,
+    TK_ERR_CAPACITY = -7         /* an output buffer is smaller than the result */
+} tk_status;
+
+typedef enum tk_dtype { TK_F64 = 0, TK_F32 = 1 } tk_dtype;
+
+/* Arithmetic of the Gram product S = Y_(n) Y_(n)^T. */
+typedef enum tk_gram_precision {
+    /* FP64 products and FP64 accumulation on FP64 matrix cores (FP32 input is
+     * widened exactly). */
+    TK_GRAM_FP64 = 0,
+    /* FP32 input only: each value x is split into bf16 hi = rne(x) and
+     * lo = rne(x - hi); the four products hh, hl, lh, ll run on bf16 matrix
+     * cores with FP32 accumulation over short chunks that are flushed into
+     * FP64 accumulators. */
+    TK_GRAM_SPLIT_BF16 = 1
+} tk_gram_precision;
+
+/* Arithmetic of the tensor-times-matrix product. */
+typedef enum tk_ttm_precision {
+    TK_TTM_FP64 = 0,   /* FP64 products and accumulation (FP64 or FP32 storage) */
+    TK_TTM_BF16 = 1,   /* FP32 storage: operands rounded to bf16, FP32 accumulation */
+    TK_TTM_BF16X3 = 2  /* FP32 storage: split bf16, products hh + hl + lh, FP32 accumulation */
+} tk_ttm_precision;
+
+/* Shape and element type of a dense tensor (dims[0] fastest in memory). */
+typedef struct tk_shape {
+    int32_t ndim;                 /* 1..TK_MAX_NDIM */
+    int32_t dtype;                /* tk_dtype */
+    int64_t dims[TK_MAX_NDIM];    /* each >= 1 */
+} tk_shape;
+
+/* ------------------------------------------------------------------ Gram */
+
+/*
+ * S = Y_(n) Y_(n)^T  (Alg. 1, Gram step; Sec. V-C computes it from the
+ * local block-column layout without permuting data, which is what this call
+ * does on the whole tensor).
+ *   y, y_dev    input tensor (F64 or F32).
+ *   mode        n, 0-based.
+ *   precision   tk_gram_precision; TK_GRAM_SPLIT_BF16 needs F32 input.
+ *   s_dev       out: J_n x J_n FP64, both triangles written (symmetric).
+ *   sumsq_dev   out (may be NULL): one FP64, the trace of S = ||Y||^2.
+ *   ws          workspace of at least gram_workspace_bytes(y, mode, precision).
+ * Deterministic: the same input gives bitwise the same S (no float atomics).
+ */
+int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, double* s_dev,
+                double* sumsq_dev, void* ws, size_t ws_bytes, void* stream);
+size_t gram_workspace_bytes(const tk_shape* y, int mode, int precision);
+
+/* ------------------------------------------------------------------- TTM */
+
+/*
+ * Z = Y x_n op(M), i.e. Z_(n) = op(M) Y_(n)  (Sec. II-A, with the matrix
+ * taken as K x J_n so that the unfolded identity holds; Sec. V-B computes it
+ * block column by block column, which is what this call does).
+ *   m_dev       FP64 column-major m_rows x m_cols.
+ *   transpose   0: op(M) = M, M is K x J_n (m_rows = K, m_cols = J_n);
+ *               1: op(M) = M^T, M is J_n x K (m_rows = J_n, m_cols = K).
+ *               ST-HOSVD applies U_n^T with transpose = 1 and M = U_n;
+ *               reconstruction applies U_n with transpose = 0.
+ *   precision   tk_ttm_precision (BF16 variants need F32 storage).
+ *   z_dev       out: Y's dims with dims[mode] = K, same dtype as Y; must not
+ *               overlap y_dev.
+ */
+int ttm_mode_n(const tk_shape* y, const void* y_dev, int mode, const double* m_dev,
+               int64_t m_rows, int64_t m_cols, int transpose, int precision, void* z_dev,
+               void* stream);
+
+/* --------------------------------------------------------------- ST-HOSVD */
+
+typedef struct tk_options {
+    double eps;                  /* relative error target, >= 0, finite */
+    const int32_t* mode_order;   /* host, ndim entries: a permutation of 0..N-1; NULL = 0..N-1 */
+    const int64_t* fixed_ranks;  /* host, ndim entries in [1, I_n]; NULL = the eps rule */
+    const int64_t* max_ranks;    /* host, ndim entries >= 1; NULL = I_n.  Sizes the
+                                    workspace; a rank above it fails with TK_ERR_CAPACITY */
+    int32_t gram_precision;      /* tk_gram_precision */
+    int32_t ttm_precision;       /* tk_ttm_precision */
+} tk_options;
+
+typedef struct tk_tucker {
+    /* device outputs, caller-allocated */
+    void* core_dev;                    /* core G, x's dtype, natural layout with dims = ranks */
+    int64_t core_capacity;             /* elements available at core_dev */
+    double* factors_dev[TK_MAX_NDIM];  /* U_n: I_n x R_n column-major; capacity I_n*I_n */
+    double* eigvals_dev;               /* sum_n I_n doubles: spectrum of each mode's Gram,
+                                          descending, mode n at offset sum_{m<n} I_m; may be NULL */
+    /* host outputs, written before sthosvd_compress returns TK_OK */
+    int64_t ranks[TK_MAX_NDIM];        /* R_n */
+    double discarded[TK_MAX_NDIM];     /* sum_{r > R_n} lambda_r at mode n */
+    double norm2;                      /* ||X||^2 */
+} tk_tucker;
+
+/*
+ * Alg. 1 (ST-HOSVD).  For each mode n in opt->mode_order: S = Y_(n) Y_(n)^T;
+ * eigendecomposition of S in FP64; R_n = min R >= 1 with
+ * sum_{r>R} lambda_r(S) <= eps^2 ||X||^2 / N (||X|| of the input, N = ndim,
+ * negative rounding eigenvalues counted as 0); U_n = the leading R_n
+ * eigenvectors (each signed so that its largest-magnitude entry is
+ * positive); Y <- Y x_n U_n^T.  The final Y is the core G.
+ *   x, x_dev    input tensor (not modified).
+ *   ws          at least sthosvd_workspace_bytes(x, opt) bytes.
+ * Synchronises `stream` before returning.  Errors: TK_ERR_CAPACITY if the
+ * core does not fit core_capacity or a rank exceeds max_ranks;
+ * TK_ERR_NONFINITE if the input holds Inf/NaN.
+ */
+int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt,
+                     tk_tucker* out, void* ws, size_t ws_bytes, void* stream);
+size_t sthosvd_workspace_bytes(const tk_shape* x, const tk_options* opt);
+
+/* ---------------------------------------------------------- reconstruction */
+
+/*
+ * X~ = G x_1 U_1 x_2 U_2 ... x_N U_N  (Sec. II-C, eq. reconstruct).  Any
+ * subset of rows of a factor gives the matching subtensor (Sec. II-C), so
+ * full_dims[n] may be smaller than the original I_n when factors_dev[n]
+ * points at a row subset (leading dimension factor_ld[n]).
+ *   core, core_dev  core tensor, dims = ranks (F64 or F32).
+ *   factors_dev[n]  FP64 column-major full_dims[n] x R_n, leading dim factor_ld[n]
+ *                   (factor_ld may be NULL: leading dim = full_dims[n]).
+ *   precision       tk_ttm_precision used for every product.
+ *   xhat_dev        out: prod(full_dims) elements of the core's dtype.
+ *   ws              at least reconstruct_workspace_bytes(core, full_dims) bytes.
+ * Asynchronous.
+ */
+int tucker_reconstruct(const tk_shape* core, const void* core_dev,
+                       const double* const* factors_dev, const int64_t* factor_ld,
+                       const int64_t* full_dims, int precision, void* xhat_dev, void* ws,
+                       size_t ws_bytes, void* stream);
+size_t reconstruct_workspace_bytes(const tk_shape* core, const int64_t* full_dims);
+
+/*
+ * Error metrics of an approximation (Table II): writes to out_host[3]
+ *   [0] ||X - X~||^2, [1] max |X - X~|, [2] ||X||^2,
+ * accumulated in FP64.  x and xhat share shape and dtype.  Synchronises the
+ * stream.  ws: at least error_metrics_workspace_bytes(x).
+ */
+int tucker_error_metrics(const tk_shape* x, const void* x_dev, const void* xhat_dev,
+                         double* out_host, void* ws, size_t ws_bytes, void* stream);
+size_t error_metrics_workspace_bytes(const tk_shape* x);
+
+/* --------------------------------------------------------------- helpers */
+
+const char* tk_status_string(int status);
+const char* tk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUCKER_H */

@@ -1,0 +1,181 @@
+// Internal helpers shared by the library's translation units: error
+// plumbing, the block-column view of a mode-n unfolding, and the column-tile
+// map that every streaming kernel (Gram, TTM) walks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "tucker.h"
+
+namespace tk {
+
+// ------------------------------------------------------------- errors
+
+void set_error(const char* fmt, ...);  // thread-local message for tk_last_error()
+int fail(int status, const char* fmt, ...);
+
+#define TK_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::tk::fail(TK_ERR_HIP, "%s failed: %s (%s:%d)", #call,            \
+                              hipGetErrorString(e_), __FILE__, __LINE__);            \
+    } while (0)
+
+#define TK_TRY(expr)                 \
+    do {                             \
+        int rc_ = (expr);            \
+        if (rc_ != TK_OK) return rc_; \
+    } while (0)
+
+// ------------------------------------------------------------- shapes
+
+inline size_t dtype_size(int dt) { return dt == TK_F64 ? 8 : 4; }
+
+inline int64_t numel(const tk_shape& s) {
+    int64_t p = 1;
+    for (int k = 0; k < s.ndim; ++k) p *= s.dims[k];
+    return p;
+}
+
+// Validates ndim, dims and dtype.  Never touches the device.
+int check_shape(const tk_shape* s, const char* what);
+
+// Block-column view of the mode-n unfolding (Sec. IV-C): the tensor read as
+// Y[B][J][L] with L = prod_{m<n} dims[m], J = dims[n], B = prod_{m>n} dims[m].
+// Column kk of the unfolding is (b, l) with kk = b * L + l; the element
+// (i, b, l) sits at offset l + L * (i + J * b).
+struct ModeView {
+    int64_t L, B;
+    int J;
+};
+
+inline ModeView mode_view(const int64_t* dims, int ndim, int n) {
+    ModeView v{1, 1, (int)dims[n]};
+    for (int k = 0; k < n; ++k) v.L *= dims[k];
+    for (int k = n + 1; k < ndim; ++k) v.B *= dims[k];
+    return v;
+}
+
+// Column tiles of KT columns over a ModeView.  Two regimes:
+//  packed  (KT % L == 0): a tile is KT/L consecutive b-blocks, one contiguous
+//          memory range of (KT/L) * J * L elements; column kk = bb * L + l.
+//  strided (otherwise):   a tile is a segment [l0, l0 + KT) of one b-block,
+//          J rows of up to KT contiguous elements with row stride L.
+struct TileMap {
+    int64_t L, B;
+    int J, KT;
+    int packed;     // 1 = packed regime
+    int nbb;        // packed: b-blocks per tile
+    int64_t lsegs;  // strided: ceil(L / KT) segments per b-block
+    int64_t ntiles;
+};
+
+inline TileMap make_tiles(const ModeView& v, int KT) {
+    TileMap t{};
+    t.L = v.L;
+    t.B = v.B;
+    t.J = v.J;
+    t.KT = KT;
+    t.packed = (v.L <= KT && KT % v.L == 0) ? 1 : 0;
+    if (t.packed) {
+        t.nbb = (int)(KT / v.L);
+        t.lsegs = 1;
+        t.ntiles = (v.B + t.nbb - 1) / t.nbb;
+    } else {
+        t.nbb = 1;
+        t.lsegs = (v.L + KT - 1) / KT;
+        t.ntiles = v.B * t.lsegs;
+    }
+    return t;
+}
+
+// Per-tile geometry, computed on the device.
+struct Tile {
+    int64_t base;  // offset of the tile's first element (packed) or of (b, i=0, l0) (strided)
+    int ncols;     // valid columns in the tile
+    int64_t nvalid;  // packed: valid contiguous elements
+};
+
+__device__ __forceinline__ Tile tile_at(const TileMap& m, int64_t t, int64_t rows) {
+    Tile r;
+    if (m.packed) {
+        int64_t b0 = t * m.nbb;
+        int64_t nb = m.B - b0 < m.nbb ? m.B - b0 : m.nbb;
+        r.base = b0 * rows * m.L;
+        r.ncols = (int)(nb * m.L);
+        r.nvalid = nb * rows * m.L;
+    } else {
+        int64_t b = t / m.lsegs;
+        int64_t l0 = (t - b * m.lsegs) * m.KT;
+        int64_t w = m.L - l0 < m.KT ? m.L - l0 : m.KT;
+        r.base = b * rows * m.L + l0;
+        r.ncols = (int)w;
+        r.nvalid = 0;
+    }
+    return r;
+}
+
+// ------------------------------------------------------------- launch
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// Workspace carving: bump allocator over the caller's buffer, 256-B aligned.
+struct Carver {
+    char* base;
+    size_t size, used;
+    explicit Carver(void* p, size_t n) : base((char*)p), size(n), used(0) {}
+    void* take(size_t bytes) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + bytes;
+        return base ? base + off : nullptr;
+    }
+    bool ok() const { return used <= size; }
+};
+
+// ------------------------------------------------------------- kernels API
+// (host-side launchers implemented in the .hip files; arguments already
+// validated by the C-ABI layer)
+
+struct GramPlan {
+    int KT, P, G, npairs, pairs_per_group, nb;
+    size_t partial_bytes;
+};
+GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes);
+int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
+                double* sumsq, void* ws, size_t ws_bytes, hipStream_t st);
+
+int launch_ttm(const void* y, int dtype, const ModeView& v, const double* m, int64_t K,
+               int64_t ldm, int transpose, int precision, void* z, hipStream_t st);
+
+// Eigendecomposition + truncation of one J x J FP64 Gram matrix (Alg. 1).
+// rank_mode: 0 = eps rule with tau = eps2_over_n * (*nu), 1 = fixed rank.
+// Writes lambda (J, descending), U (J x R column-major, ld J) into u_out,
+// R to *rank_out and the discarded tail sum to *disc_out (device).
+struct EigArgs {
+    const double* s;
+    int J;
+    const double* nu;      // device scalar ||X||^2
+    double eps2_over_n;    // eps^2 / N
+    int fixed_rank;        // > 0: fixed
+    int max_rank;          // capacity bound; larger R sets the capacity flag
+    double* lambda;        // J
+    double* u;             // J x R (capacity J * J)
+    int64_t* rank_out;     // device
+    double* disc_out;      // device
+    int* flags;            // device status flags (bit 0: no convergence, bit 1: capacity)
+    double* scratch;       // eig_scratch_doubles(J)
+};
+size_t eig_scratch_doubles(int J);
+int launch_eig(const EigArgs& a, hipStream_t st);
+
+int launch_error_metrics(const void* x, const void* xh, int dtype, int64_t n, double* partial,
+                         int nblocks, double* out3, hipStream_t st);
+int error_metrics_blocks(int64_t n);
+
+}  // namespace tk

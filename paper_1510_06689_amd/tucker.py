@@ -1,0 +1,379 @@
+"""Python binding of the C-ABI in ``include/tucker.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libtucker.so``.  torch supplies device memory (outputs and
+workspaces) and the stream (the current torch stream of the tensor's device).
+
+Tensors use the paper's layout: logical shape ``(I_1, ..., I_N)`` with mode 1
+fastest in memory (Fortran strides), e.g.
+``torch.empty(I_N, ..., I_1, device="cuda").permute(N-1, ..., 0)``.
+Factor matrices are FP64 ``I_n x R_n`` tensors with column-major strides.
+
+Importing this module does not need a GPU; calling the compute functions
+does.  A missing library raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtucker.so")
+
+MAX_NDIM = 8
+F64, F32 = 0, 1
+GRAM_PRECISIONS = {"fp64": 0, "split_bf16": 1}
+TTM_PRECISIONS = {"fp64": 0, "bf16": 1, "bf16x3": 2}
+STATUS = {0: "TK_OK", -1: "TK_ERR_INVALID_ARG", -2: "TK_ERR_UNSUPPORTED",
+          -3: "TK_ERR_WORKSPACE", -4: "TK_ERR_HIP", -5: "TK_ERR_NONFINITE",
+          -6: "TK_ERR_EIG_NO_CONVERGENCE", -7: "TK_ERR_CAPACITY"}
+
+EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "ttm_mode_n", "sthosvd_compress",
+           "sthosvd_workspace_bytes", "tucker_reconstruct", "reconstruct_workspace_bytes",
+           "tucker_error_metrics", "error_metrics_workspace_bytes", "tk_status_string",
+           "tk_last_error")
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * MAX_NDIM)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("mode_order", ctypes.POINTER(ctypes.c_int32)),
+                ("fixed_ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("max_ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("gram_precision", ctypes.c_int32), ("ttm_precision", ctypes.c_int32)]
+
+
+class Tucker(ctypes.Structure):
+    _fields_ = [("core_dev", ctypes.c_void_p), ("core_capacity", ctypes.c_int64),
+                ("factors_dev", ctypes.c_void_p * MAX_NDIM), ("eigvals_dev", ctypes.c_void_p),
+                ("ranks", ctypes.c_int64 * MAX_NDIM), ("discarded", ctypes.c_double * MAX_NDIM),
+                ("norm2", ctypes.c_double)]
+
+
+_lib = None
+_vp, _sz, _i64, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int
+_pshape = ctypes.POINTER(Shape)
+
+
+def library() -> ctypes.CDLL:
+    """Load ``libtucker.so`` (built by ``python -m paper_1510_06689_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1510_06689_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "gram_mode_n": (_int, [_pshape, _vp, _int, _int, _vp, _vp, _vp, _sz, _vp]),
+        "gram_workspace_bytes": (_sz, [_pshape, _int, _int]),
+        "ttm_mode_n": (_int, [_pshape, _vp, _int, _vp, _i64, _i64, _int, _int, _vp, _vp]),
+        "sthosvd_compress": (_int, [_pshape, _vp, ctypes.POINTER(Options),
+                                    ctypes.POINTER(Tucker), _vp, _sz, _vp]),
+        "sthosvd_workspace_bytes": (_sz, [_pshape, ctypes.POINTER(Options)]),
+        "tucker_reconstruct": (_int, [_pshape, _vp, ctypes.POINTER(_vp),
+                                      ctypes.POINTER(_i64), ctypes.POINTER(_i64), _int, _vp,
+                                      _vp, _sz, _vp]),
+        "reconstruct_workspace_bytes": (_sz, [_pshape, ctypes.POINTER(_i64)]),
+        "tucker_error_metrics": (_int, [_pshape, _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                        _vp, _sz, _vp]),
+        "error_metrics_workspace_bytes": (_sz, [_pshape]),
+        "tk_status_string": (ctypes.c_char_p, [_int]),
+        "tk_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = library().tk_last_error().decode(errors="replace")
+        raise TuckerError(status, msg)
+
+
+# ------------------------------------------------------------ marshalling
+
+def is_fortran(x: torch.Tensor) -> bool:
+    expect = 1
+    for d, s in zip(x.shape, x.stride()):
+        if d != 1 and s != expect:
+            return False
+        expect *= d
+    return True
+
+
+def empty_fortran(dims: Sequence[int], dtype, device) -> torch.Tensor:
+    n = len(dims)
+    return torch.empty(tuple(reversed(list(dims))), dtype=dtype, device=device).permute(
+        *reversed(range(n)))
+
+
+def empty_colmajor(rows: int, cols: int, device, dtype=torch.float64) -> torch.Tensor:
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}; use float64 or float32")
+
+
+def shape_of(x: torch.Tensor, dims: Optional[Sequence[int]] = None,
+             dtype: Optional[int] = None) -> Shape:
+    s = Shape()
+    dims = list(x.shape) if dims is None else list(dims)
+    if not 1 <= len(dims) <= MAX_NDIM:
+        raise ValueError(f"ndim must be in [1, {MAX_NDIM}]")
+    s.ndim = len(dims)
+    s.dtype = _dtype_code(x) if dtype is None else dtype
+    for k, d in enumerate(dims):
+        s.dims[k] = int(d)
+    return s
+
+
+def _require_device(*ts: torch.Tensor):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensors must live on a GPU device")
+        if not is_fortran(t):
+            raise ValueError("tensors must be densely packed with mode 1 fastest "
+                             "(Fortran strides)")
+
+
+def _stream(dev) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _workspace(nbytes: int, dev) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=dev)
+    return ws
+
+
+def _aligned(ws: torch.Tensor) -> int:
+    p = ws.data_ptr()
+    return (p + 255) & ~255
+
+
+# ------------------------------------------------------------------- API
+
+def gram(y: torch.Tensor, mode: int, precision: str = "fp64"):
+    """``S = Y_(n) Y_(n)^T`` (FP64, J x J) and ``||Y||^2`` (FP64 scalar tensor)."""
+    _require_device(y)
+    lib = library()
+    sh = shape_of(y)
+    prec = GRAM_PRECISIONS[precision]
+    need = lib.gram_workspace_bytes(ctypes.byref(sh), mode, prec)
+    if need == 0:
+        _check(lib.gram_mode_n(ctypes.byref(sh), y.data_ptr(), mode, prec, None, None, None, 0,
+                               None))
+    j = y.shape[mode]
+    s = torch.empty((j, j), dtype=torch.float64, device=y.device)
+    sumsq = torch.empty((), dtype=torch.float64, device=y.device)
+    ws = _workspace(need, y.device)
+    _check(lib.gram_mode_n(ctypes.byref(sh), y.data_ptr(), mode, prec, s.data_ptr(),
+                           sumsq.data_ptr(), _aligned(ws), need, _stream(y.device)))
+    return s, sumsq
+
+
+def ttm(y: torch.Tensor, mode: int, m: torch.Tensor, transpose: bool = True,
+        precision: str = "fp64") -> torch.Tensor:
+    """``Z = Y x_n op(M)``; ``op(M) = M^T`` when ``transpose`` (M is J_n x K),
+    else ``M`` (K x J_n).  M is FP64 and column-major."""
+    _require_device(y)
+    if m.dtype != torch.float64 or m.dim() != 2 or not is_fortran(m):
+        raise ValueError("M must be a column-major FP64 matrix")
+    lib = library()
+    sh = shape_of(y)
+    rows, cols = m.shape
+    k = cols if transpose else rows
+    zd = list(y.shape)
+    zd[mode] = k
+    z = empty_fortran(zd, y.dtype, y.device)
+    _check(lib.ttm_mode_n(ctypes.byref(sh), y.data_ptr(), mode, m.data_ptr(), rows, cols,
+                          int(transpose), TTM_PRECISIONS[precision], z.data_ptr(),
+                          _stream(y.device)))
+    return z
+
+
+@dataclass
+class TuckerTensor:
+    core: torch.Tensor            # dims = ranks, same dtype as the input
+    factors: list                 # U_n: FP64 I_n x R_n, column-major
+    ranks: tuple
+    eigvals: list                 # per-mode Gram spectra (FP64, descending)
+    discarded: tuple              # discarded eigenvalue mass per mode
+    norm2: float                  # ||X||^2
+
+    @property
+    def full_dims(self):
+        return tuple(int(u.shape[0]) for u in self.factors)
+
+
+def _options(ndim, eps, order, ranks, max_ranks, gram_precision, ttm_precision, keep):
+    opt = Options()
+    opt.eps = float(eps)
+    if order is not None:
+        a = (ctypes.c_int32 * ndim)(*[int(v) for v in order])
+        keep.append(a)
+        opt.mode_order = ctypes.cast(a, ctypes.POINTER(ctypes.c_int32))
+    if ranks is not None:
+        a = (ctypes.c_int64 * ndim)(*[int(v) for v in ranks])
+        keep.append(a)
+        opt.fixed_ranks = ctypes.cast(a, ctypes.POINTER(ctypes.c_int64))
+    if max_ranks is not None:
+        a = (ctypes.c_int64 * ndim)(*[int(v) for v in max_ranks])
+        keep.append(a)
+        opt.max_ranks = ctypes.cast(a, ctypes.POINTER(ctypes.c_int64))
+    opt.gram_precision = GRAM_PRECISIONS[gram_precision]
+    opt.ttm_precision = TTM_PRECISIONS[ttm_precision]
+    return opt
+
+
+class Compressor:
+    """ST-HOSVD (Alg. 1) with preallocated outputs and workspace, reusable
+    across calls on tensors of the same shape (the benchmark's timed step)."""
+
+    def __init__(self, dims: Sequence[int], dtype, device, eps: float, order=None, ranks=None,
+                 max_ranks=None, gram_precision: str = "fp64", ttm_precision: str = "fp64"):
+        self.dims = tuple(int(d) for d in dims)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        n = len(self.dims)
+        self._keep = []
+        self.opt = _options(n, eps, order, ranks, max_ranks, gram_precision, ttm_precision,
+                            self._keep)
+        probe = torch.empty(0, dtype=dtype)
+        self.shape = shape_of(probe, self.dims, _dtype_code(probe))
+        lib = library()
+        need = lib.sthosvd_workspace_bytes(ctypes.byref(self.shape), ctypes.byref(self.opt))
+        if need == 0:  # invalid arguments: let the entry point report why
+            _check(lib.sthosvd_compress(ctypes.byref(self.shape), None, ctypes.byref(self.opt),
+                                        None, None, 0, None))
+        self.ws_bytes = need
+        self.ws = _workspace(need, self.device)
+        caps = [min(d, int(max_ranks[k])) if max_ranks is not None else d
+                for k, d in enumerate(self.dims)]
+        if ranks is not None:
+            caps = [int(r) for r in ranks]
+        self.core_capacity = math.prod(caps)
+        self.core_buf = torch.empty(self.core_capacity, dtype=dtype, device=self.device)
+        self.factor_bufs = [torch.empty(d * d, dtype=torch.float64, device=self.device)
+                            for d in self.dims]
+        self.eig_buf = torch.empty(sum(self.dims), dtype=torch.float64, device=self.device)
+        self.out = Tucker()
+        self.out.core_dev = self.core_buf.data_ptr()
+        self.out.core_capacity = self.core_capacity
+        for k, f in enumerate(self.factor_bufs):
+            self.out.factors_dev[k] = f.data_ptr()
+        self.out.eigvals_dev = self.eig_buf.data_ptr()
+
+    def run(self, x: torch.Tensor) -> None:
+        """One ST-HOSVD of ``x``; synchronises the current stream."""
+        if tuple(x.shape) != self.dims or x.dtype != self.dtype:
+            raise ValueError("tensor does not match the compressor's shape/dtype")
+        _require_device(x)
+        _check(library().sthosvd_compress(ctypes.byref(self.shape), x.data_ptr(),
+                                          ctypes.byref(self.opt), ctypes.byref(self.out),
+                                          _aligned(self.ws), self.ws_bytes,
+                                          _stream(self.device)))
+
+    def result(self) -> TuckerTensor:
+        n = len(self.dims)
+        ranks = tuple(int(self.out.ranks[k]) for k in range(n))
+        core = self.core_buf[:math.prod(ranks)].view(tuple(reversed(ranks))).permute(
+            *reversed(range(n)))
+        factors = [self.factor_bufs[k][:self.dims[k] * ranks[k]].view(ranks[k], self.dims[k]).t()
+                   for k in range(n)]
+        eig, off = [], 0
+        for d in self.dims:
+            eig.append(self.eig_buf[off:off + d])
+            off += d
+        return TuckerTensor(core, factors, ranks, eig,
+                            tuple(float(self.out.discarded[k]) for k in range(n)),
+                            float(self.out.norm2))
+
+
+def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
+            gram_precision: str = "fp64", ttm_precision: str = "fp64") -> TuckerTensor:
+    """Alg. 1 (ST-HOSVD) of ``x`` on its GPU.  Returns copies of the outputs."""
+    c = Compressor(x.shape, x.dtype, x.device, eps, order, ranks, max_ranks, gram_precision,
+                   ttm_precision)
+    c.run(x)
+    r = c.result()
+    return TuckerTensor(_fortran_copy(r.core), [_fortran_copy(f) for f in r.factors], r.ranks,
+                        [e.clone() for e in r.eigvals], r.discarded, r.norm2)
+
+
+def _fortran_copy(t: torch.Tensor) -> torch.Tensor:
+    out = empty_fortran(t.shape, t.dtype, t.device)
+    out.copy_(t)
+    return out
+
+
+def reconstruct(core: torch.Tensor, factors: Sequence[torch.Tensor], full_dims=None,
+                precision: str = "fp64") -> torch.Tensor:
+    """``X~ = G x_1 U_1 ... x_N U_N`` (Sec. II-C).  A factor may be a row
+    subset (any FP64 column-major view), which yields the matching subtensor."""
+    _require_device(core)
+    n = core.dim()
+    if len(factors) != n:
+        raise ValueError("one factor per mode")
+    lds = []
+    for k, u in enumerate(factors):
+        if u.dtype != torch.float64 or u.dim() != 2 or u.stride(0) != 1 or u.shape[1] != \
+                core.shape[k]:
+            raise ValueError(f"factor {k} must be a column-major FP64 I_n x R_n matrix")
+        lds.append(max(u.stride(1), u.shape[0]) if u.shape[1] > 1 else u.shape[0])
+    full = [int(u.shape[0]) for u in factors] if full_dims is None else list(full_dims)
+    lib = library()
+    sh = shape_of(core)
+    fd = (ctypes.c_int64 * n)(*full)
+    ld = (ctypes.c_int64 * n)(*lds)
+    ptrs = (ctypes.c_void_p * n)(*[u.data_ptr() for u in factors])
+    need = lib.reconstruct_workspace_bytes(ctypes.byref(sh), fd)
+    ws = _workspace(need, core.device)
+    out = empty_fortran(full, core.dtype, core.device)
+    _check(lib.tucker_reconstruct(ctypes.byref(sh), core.data_ptr(), ptrs, ld, fd,
+                                  TTM_PRECISIONS[precision], out.data_ptr(), _aligned(ws), need,
+                                  _stream(core.device)))
+    return out
+
+
+def error_metrics(x: torch.Tensor, xhat: torch.Tensor):
+    """``(||X - X~||^2, max|X - X~|, ||X||^2)`` accumulated in FP64."""
+    _require_device(x, xhat)
+    if x.shape != xhat.shape or x.dtype != xhat.dtype:
+        raise ValueError("x and xhat must match in shape and dtype")
+    lib = library()
+    sh = shape_of(x)
+    need = lib.error_metrics_workspace_bytes(ctypes.byref(sh))
+    ws = _workspace(need, x.device)
+    out = (ctypes.c_double * 3)()
+    _check(lib.tucker_error_metrics(ctypes.byref(sh), x.data_ptr(), xhat.data_ptr(), out,
+                                    _aligned(ws), need, _stream(x.device)))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def compression_ratio(dims, ranks) -> float:
+    """``prod I_n / (prod R_n + sum I_n R_n)`` (Sec. VII-B)."""
+    return math.prod(dims) / (math.prod(ranks) + sum(i * r for i, r in zip(dims, ranks)))

@@ -1,0 +1,209 @@
+"""GPU parity: every entry point of the C-ABI against the FP64 CPU oracle on
+the same seeded inputs, element by element.  Shapes cover every tile regime
+of the kernels (mode 1 with contiguous columns, short packed rows, long
+strided rows), several tiles per workgroup and ragged tails (extents that are
+not multiples of the 16-row blocks or 32-column tiles), extents 1 and the
+largest supported extent, FP64 and FP32 storage."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1510_06689_amd import tucker
+from gpu_util import U32, U64, gram_tolerance, say, to_dev, to_host, ttm_tolerance
+
+pytestmark = pytest.mark.gpu
+
+GRAM_CASES = [
+    ((32, 32, 32), None),
+    ((5, 7, 3), None),
+    ((128, 64, 16), None),
+    ((40, 33, 37, 6), None),
+    ((3, 16, 100), None),
+    ((2, 200, 5), None),
+    ((16, 300, 3), (1,)),
+    ((1, 20, 1), None),
+    ((7,), None),
+    ((512, 3), (0,)),
+    ((130, 2, 2, 9), None),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dims,modes", GRAM_CASES)
+def test_gram_matches_oracle(dims, modes, dtype):
+    x = synth.random_tensor(dims, seed=sum(dims), dtype=dtype)
+    xh = x.double().numpy()
+    xd = to_dev(x)
+    nu = oracle.norm2(xh)
+    for n in (range(len(dims)) if modes is None else modes):
+        say(f"gram dims={dims} mode={n} dtype={dtype}")
+        s, sumsq = tucker.gram(xd, n)
+        torch.cuda.synchronize()
+        s = s.cpu().numpy()
+        ref = oracle.gram(xh, n)
+        k = xh.size // dims[n]
+        tol = gram_tolerance(ref, k)
+        err = np.abs(s - ref)
+        assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
+        assert np.array_equal(s, s.T)
+        assert math.isclose(float(sumsq.item()), nu, rel_tol=(xh.size + 2) * U64)
+
+
+def test_gram_is_deterministic():
+    x = to_dev(synth.random_tensor((96, 40, 50), seed=5))
+    for n in range(3):
+        a, _ = tucker.gram(x, n)
+        b, _ = tucker.gram(x, n)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+TTM_CASES = [
+    ((32, 32, 32), 0, 4), ((32, 32, 32), 1, 5), ((32, 32, 32), 2, 6),
+    ((5, 7, 3), 1, 2), ((128, 64, 16), 0, 16), ((128, 64, 16), 1, 17),
+    ((128, 64, 16), 2, 40), ((40, 33, 37, 6), 0, 3), ((40, 33, 37, 6), 1, 64),
+    ((40, 33, 37, 6), 2, 100), ((40, 33, 37, 6), 3, 6), ((3, 16, 100), 1, 1),
+    ((2, 200, 5), 1, 300), ((16, 300, 3), 1, 33), ((7,), 0, 3), ((512, 3), 0, 20),
+    ((20, 30, 2), 2, 300), ((64, 9, 18), 0, 64),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("transpose", [True, False])
+@pytest.mark.parametrize("dims,n,k", TTM_CASES)
+def test_ttm_matches_oracle(dims, n, k, transpose, dtype):
+    say(f"ttm dims={dims} mode={n} K={k} transpose={transpose} dtype={dtype}")
+    x = synth.random_tensor(dims, seed=3 * sum(dims) + k, dtype=dtype)
+    xh = x.double().numpy()
+    rng = np.random.default_rng(k)
+    v = rng.standard_normal((k, dims[n]))           # op(M), K x J_n
+    m = v.T if transpose else v
+    md = torch.as_tensor(np.asfortranarray(m)).to("cuda:0")
+    md = tucker.empty_colmajor(m.shape[0], m.shape[1], "cuda:0").copy_(md)
+    z = tucker.ttm(to_dev(x), n, md, transpose=transpose)
+    torch.cuda.synchronize()
+    ref = oracle.ttm(xh, n, v)
+    tol = ttm_tolerance(xh, n, v)
+    if dtype == torch.float32:  # output rounded to FP32 once
+        tol = tol + U32 * np.abs(ref)
+    err = np.abs(to_host(z).astype(np.float64) - ref)
+    assert err.shape == ref.shape
+    assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
+
+
+def _compare_tucker(xh, res, ref, eps_sym):
+    """Compare a GPU ST-HOSVD with the oracle's: ranks exactly; spectra and
+    reconstructions within FP64 perturbation bounds."""
+    assert res.ranks == ref.ranks
+    n = xh.ndim
+    nu = ref.norm2
+    assert math.isclose(res.norm2, nu, rel_tol=(xh.size + 2) * U64)
+    kappa = 1.0
+    for k in range(n):
+        lam = res.eigvals[k].cpu().numpy()
+        lref = ref.eigvals[k]
+        # Weyl: |d lambda| <= ||dS||, with ||dS|| <= J * K u ||S||
+        jn = xh.shape[k]
+        tol = 64 * jn * U64 * max(abs(lref[0]), 1e-300) * 8
+        assert np.all(np.abs(lam - lref) <= tol + 1e-13 * abs(lref[0])), (k, np.abs(lam - lref).max())
+        r = ref.ranks[k]
+        gap = lref[r - 1] - (lref[r] if r < jn else 0.0)
+        if gap > 0:
+            kappa = max(kappa, lref[0] / gap)
+        u = res.factors[k].cpu().numpy()
+        np.testing.assert_allclose(u.T @ u, np.eye(r), atol=64 * jn * U64)
+    xg = tucker.reconstruct(res.core, res.factors)
+    xr = oracle.reconstruct(ref.core, ref.factors)
+    diff = np.linalg.norm((to_host(xg) - xr).ravel())
+    bound = 1e3 * n * U64 * kappa * math.sqrt(nu)
+    assert diff <= bound, f"reconstruction differs by {diff:.3e} > {bound:.3e}"
+    np.testing.assert_allclose(np.array(res.discarded), ref.discarded,
+                               atol=1e3 * U64 * kappa * nu)
+    return xg
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_sthosvd_planted32(seed):
+    w = synth.WORKLOADS["planted32"]
+    say(f"sthosvd planted32 seed={seed}")
+    x = w.make(seed=seed)
+    xh = x.numpy()
+    res = tucker.sthosvd(to_dev(x), w.eps)
+    ref = oracle.sthosvd(xh, w.eps)
+    assert res.ranks == w.ranks
+    xg = _compare_tucker(xh, res, ref, w.eps)
+    e2, mx, n2 = tucker.error_metrics(to_dev(x), xg)
+    re2, rmx, rn2 = oracle.error_metrics(xh, to_host(xg))
+    assert math.isclose(e2, re2, rel_tol=1e-9) and math.isclose(n2, rn2, rel_tol=1e-12)
+    assert mx == rmx
+    assert math.sqrt(e2 / n2) <= w.eps
+
+
+STHOSVD_CASES = [
+    # dims, ranks, rho, eps, order, fixed ranks
+    ((40, 33, 37, 6), (5, 4, 6, 2), 0.7, 1e-3, None, None),
+    ((40, 33, 37, 6), (5, 4, 6, 2), 0.7, 1e-3, (3, 1, 0, 2), None),
+    ((24, 20, 18), (3, 3, 3), 1.0, 0.0, None, None),             # eps = 0: full ranks
+    ((24, 20, 18), (3, 3, 3), 1.0, 1e-2, None, (5, 2, 7)),        # fixed ranks
+    ((64, 16, 12, 5), (8, 4, 3, 2), 0.6, 1e-4, (1, 3, 0, 2), None),
+    ((1, 30, 9), (1, 4, 3), 0.8, 1e-3, None, None),               # extent-1 mode
+    ((50,), (5,), 1.0, 1e-2, None, None),                         # N = 1
+    ((130, 70), (10, 10), 0.5, 1e-5, None, None),                 # N = 2, ragged blocks
+    ((8, 8, 8, 8, 8), (2, 3, 2, 3, 2), 0.9, 1e-3, (4, 3, 2, 1, 0), None),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,rho,eps,order,fixed", STHOSVD_CASES)
+def test_sthosvd_matches_oracle(dims, ranks, rho, eps, order, fixed):
+    say(f"sthosvd dims={dims} eps={eps} order={order} fixed={fixed}")
+    x = synth.planted_tucker(dims, ranks, rho=rho, noise=1e-4, seed=len(dims) + sum(dims))
+    xh = x.numpy()
+    res = tucker.sthosvd(to_dev(x), eps, order=order, ranks=fixed)
+    ref = oracle.sthosvd(xh, eps, order=order, ranks=fixed)
+    _compare_tucker(xh, res, ref, eps)
+
+
+def test_sthosvd_fp32_storage_fp64_compute():
+    """FP32 storage with FP64 arithmetic: the oracle sees the same FP32 values
+    widened; TTM outputs round to FP32 after every mode."""
+    w = synth.WORKLOADS["planted32"]
+    x32 = w.make(dtype=torch.float32)
+    xh = x32.double().numpy()
+    res = tucker.sthosvd(to_dev(x32), w.eps)
+    ref = oracle.sthosvd(xh, w.eps)
+    assert res.ranks == ref.ranks
+    for k in range(3):
+        lam = res.eigvals[k].cpu().numpy()
+        # after the first mode the working tensor carries FP32 rounding
+        assert np.all(np.abs(lam - ref.eigvals[k]) <= 1e-5 * ref.eigvals[k][0])
+
+
+def test_reconstruct_matches_oracle_and_subtensor():
+    x = synth.planted_tucker((30, 20, 10), (4, 3, 2), rho=0.8, noise=1e-3, seed=9).numpy()
+    ref = oracle.sthosvd(x, 1e-2)
+    core = to_dev(ref.core)
+    facs = [tucker.empty_colmajor(u.shape[0], u.shape[1], "cuda:0").copy_(torch.as_tensor(u))
+            for u in ref.factors]
+    xg = tucker.reconstruct(core, facs)
+    xr = oracle.reconstruct(ref.core, ref.factors)
+    tol = 64 * U64 * np.abs(xr).max() * 30
+    assert np.abs(to_host(xg) - xr).max() <= tol
+    # subtensor from row subsets (Sec. II-C): rows 5..14 of mode 1, rows 3..5 of mode 3
+    sub = [facs[0][5:15], facs[1], facs[2][3:6]]
+    xs = tucker.reconstruct(core, sub)
+    assert np.abs(to_host(xs) - xr[5:15, :, 3:6]).max() <= tol
+
+
+def test_invalid_on_device_inputs_raise():
+    x = to_dev(synth.random_tensor((8, 8), seed=1))
+    with pytest.raises(tucker.TuckerError):
+        tucker.sthosvd(x, -1.0)
+    bad = x.clone()
+    bad[3, 3] = float("nan")
+    with pytest.raises(tucker.TuckerError) as e:
+        tucker.sthosvd(bad, 1e-3)
+    assert e.value.status == -5

@@ -86,7 +86,7 @@ def test_fold_inverts_unfold():
 # --------------------------------------------------------------------- TTM
 
 @pytest.mark.parametrize("shape,n,k", [((4, 5, 6), 0, 3), ((4, 5, 6), 1, 7), ((4, 5, 6), 2, 2),
-                                       ((3, 2, 4, 5), 2, 6), ((6,), 0, 2)])
+                                       ((4, 5, 6), 1, 5), ((3, 2, 4, 5), 2, 6), ((6,), 0, 2)])
 def test_ttm_against_tensordot(shape, n, k):
     x = rng_tensor(shape, 2)
     v = np.random.default_rng(3).standard_normal((k, shape[n]))
