@@ -2,19 +2,28 @@
 // (Alg. 1, eigenvector and rank steps; Sec. V-D uses a LAPACK subset solver,
 // this is the same family of method on one workgroup):
 //
-//   1. Householder reduction to tridiagonal form T = Q^T S Q (matrix in LDS
-//      for J <= 128, otherwise in global scratch), reflectors kept below the
-//      diagonal;
-//   2. all eigenvalues of T by multisection of Sturm counts (groups of
-//      threads per eigenvalue, ballots combine the sub-interval tests);
+//   1. Householder reduction to tridiagonal form T = Q^T S Q.  Each step
+//      forms A22 x (x = the pivot row, read from the upper part) and |x|^2
+//      in one pass, derives the reflector, then applies the symmetric
+//      rank-2 update with a commutative formula so A stays exactly
+//      symmetric (three barriers per step).  The matrix lives in LDS for
+//      J <= 128, otherwise in global scratch; reflector k is kept in
+//      column k below the diagonal and copied to global scratch at the end;
+//   2. all eigenvalues of T by multisection: groups of threads per
+//      eigenvalue evaluate Sturm counts with the three-term determinant
+//      recurrence of T scaled by a power of two (exact), rescaled by 2^+-300
+//      every four steps; a ballot picks the sub-interval;
 //   3. rank rule R = min R >= 1 with sum_{r>R} max(lambda_r,0) <= eps^2 nu / N
 //      (tail sums accumulated smallest first), or a fixed rank;
-//   4. the R leading eigenvectors of T by inverse iteration with partial-
-//      pivoting tridiagonal LU, re-orthogonalised inside eigenvalue clusters
-//      after every sweep;
-//   5. back-transformation by Q, and a sign rule (largest |entry| positive,
-//      lowest index on ties).
-// A single workgroup of 1024 threads; no host synchronisation.
+//   4. the R leading eigenvectors of T by inverse iteration (tridiagonal LU
+//      with partial pivoting kept in LDS, reciprocal pivots, two sweeps),
+//      in batches that fit in LDS, then modified Gram-Schmidt (twice) inside
+//      eigenvalue clusters by one wave;
+//   5. back-transformation X <- Q X, one wave per eigenvector with the
+//      vector in registers (no barriers), and a sign rule (largest |entry|
+//      positive, lowest index on ties), written to the factor output.
+// Barriers never wait on global stores inside loops: global memory is only
+// written between phases.  One workgroup of 1024 threads; no host sync.
 #include <cfloat>
 
 #include "tk_common.hpp"
@@ -23,25 +32,47 @@ namespace tk {
 
 constexpr int kEigThreads = 1024;
 constexpr int kEigWaves = kEigThreads / 64;
-constexpr int kInvIters = 3;
+constexpr int kInvIters = 2;
+constexpr int kLuArrays = 6;  // u0 (reciprocal), u1, u2, multiplier, pivot flag, x
+constexpr int kMaxVecSlots = TK_MAX_MODE_DIM / 64;  // per-lane elements of one vector
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// Moves a double across lanes with one DPP pattern (applied to both 32-bit
+// halves); lanes the pattern does not write receive 0.
+template <int CTRL, int ROW_MASK, bool BOUND_CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long bits = __double_as_longlong(v);
+    int lo = (int)(bits & 0xffffffffll), hi = (int)(bits >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Block-wide sum in a fixed order; every thread gets the result.
-__device__ double block_sum(double v, double* red) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kEigWaves; ++w) t += red[w];
-    return t;
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave, in a fixed order, returned to every lane.
+// Row prefix sums by row_shr 1, 2, 4, 8 leave each 16-lane row's total in its
+// lane 15; row_bcast 15 and 31 then carry the row totals into lane 63.  Must
+// be called with all lanes active.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0x111, 0xf, true>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf, true>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf, true>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf, true>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+    return read_lane(v, 63);
+}
+
+// 1/q from the hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ double recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    double err = fma(-q, r, 1.0);
+    return fma(r, err, r);
 }
 
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
@@ -53,50 +84,117 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
 }
 
 size_t eig_scratch_doubles(int J) {
-    // A (J*J) + X (J*J) + LU arrays l, u0, u1, u2, piv (5 * J*J)
-    return (size_t)7 * J * J + 64;
+    // A (J*J, used when J > 128) + reflectors H (J*J)
+    return (size_t)2 * J * J + 64;
+}
+
+// small per-matrix arrays + the [C][rb] partial sums of the tridiagonal step
+static size_t eig_small_doubles(int J) { return (size_t)10 * J + 64 + 8 + (size_t)kEigThreads; }
+
+// LDS doubles for the matrix (J <= 128) and later the inverse-iteration
+// batch; region + small arrays stay within the 160 KB of LDS.
+static size_t eig_region_doubles(int J) {
+    const size_t lds_doubles = 160 * 1024 / sizeof(double);
+    size_t cap = lds_doubles - eig_small_doubles(J) - 128;
+    if (cap > 16384) cap = 16384;                 // J <= 128 also holds A here (J*J <= 16384)
+    const size_t want = (size_t)kLuArrays * J * J;  // room for every vector in one batch
+    return want < cap ? want : cap;
+}
+
+// Number of eigenvalues of the (scaled) tridiagonal matrix below x: sign
+// changes along the leading principal minors
+//   p_0 = 1,  p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}.
+// An exactly zero minor is replaced by +2^-600: over that step and the next
+// one the number of sign changes is the same whichever sign a zero takes (it
+// is one), a zero last minor (x an eigenvalue) is correctly not counted, and
+// a zero followed by e_i = 0 restarts the next block from a tiny value.  The
+// pair (p_{i-1}, p_i) is rescaled by 2^+-300 every four steps (exact).
+__device__ __forceinline__ int sturm_count(const double* __restrict__ ds,
+                                           const double* __restrict__ e2s, int J, double x) {
+    constexpr double kUp = 0x1p300, kDown = 0x1p-300, kZero = 0x1p-600;
+    double p0 = 1.0, p1 = ds[0] - x;
+    p1 = p1 == 0.0 ? kZero : p1;
+    bool neg = p1 < 0.0;
+    int c = (int)neg;
+    auto step = [&](double di, double ei2) {
+        double p2 = fma(di - x, p1, -ei2 * p0);
+        p2 = p2 == 0.0 ? kZero : p2;
+        const bool n2 = p2 < 0.0;
+        c += (int)(n2 != neg);
+        neg = n2;
+        p0 = p1;
+        p1 = p2;
+    };
+    int i = 1;
+    for (; i + 3 < J; i += 4) {  // four steps per trip: the eight loads go out together
+        const double d0 = ds[i], d1 = ds[i + 1], d2 = ds[i + 2], d3 = ds[i + 3];
+        const double f0 = e2s[i - 1], f1 = e2s[i], f2 = e2s[i + 1], f3 = e2s[i + 2];
+        step(d0, f0);
+        step(d1, f1);
+        step(d2, f2);
+        step(d3, f3);
+        const double mg = fmax(fabs(p0), fabs(p1));
+        const double f = mg > kUp ? kDown : (mg < kDown ? kUp : 1.0);
+        p0 *= f;
+        p1 *= f;
+    }
+    for (; i < J; ++i) step(ds[i], e2s[i - 1]);
+    return c;
 }
 
 template <bool A_IN_LDS>
-__global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a) {
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region) {
     extern __shared__ double smem[];
     const int J = a.J;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* A = A_IN_LDS ? smem : a.scratch;  // row-major J x J
-    double* sv = A_IN_LDS ? smem + (size_t)J * J : smem;
+    double* reg = smem;                        // A (J <= 128) then the LU batch
+    double* sv = smem + region;
     double* d = sv;              // J
     double* e = d + J;           // J
-    double* e2 = e + J;          // J
+    double* e2 = e + J;          // J (scaled)
     double* beta = e2 + J;       // J
-    double* vb = beta + J;       // J
-    double* pw = vb + J;         // J
+    double* pw = beta + J;       // J: A22 x
     double* lam = pw + J;        // J (descending)
     double* shift = lam + J;     // J
-    double* dots = shift + J;    // J
-    double* red = dots + J;      // 64
+    double* dots = shift + J;    // J: v during step 1, scaled d during step 2
+    double* colv = dots + J;     // J: w during step 1
+    double* red = colv + J;      // 64
     int* misc = (int*)(red + 64);  // [0] = R
-    double* X = a.scratch + (size_t)J * J;  // [t][j], column j is vector j
-    double* Lm = X + (size_t)J * J;
-    double* U0 = Lm + (size_t)J * J;
-    double* U1 = U0 + (size_t)J * J;
-    double* U2 = U1 + (size_t)J * J;
-    double* PV = U2 + (size_t)J * J;
+    double* A = A_IN_LDS ? reg : a.scratch;   // row-major J x J
+    double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
+    double* X = a.u;                          // column-major J x R
 
     // ---- load S (symmetric) -------------------------------------------
     for (int idx = tid; idx < J * J; idx += kEigThreads) A[idx] = a.s[idx];
     __syncthreads();
 
     // ---- 1. Householder tridiagonalisation ------------------------------
+    // Column-chunked matrix-vector product: thread t owns row i = t % RB of
+    // A22 and the columns j = c, c + C, ... with c = t / RB; the C partials
+    // of each row are added in a fixed order by whoever needs them.
+    int rb = 32;
+    while (rb < J) rb *= 2;
+    const int C = kEigThreads / rb;  // chunks per row
+    const int mi = tid % rb, mc = tid / rb;
+    double* part = red + 64 + 8;  // [C][rb] = kEigThreads partial sums, after misc
+    double* pp = colv;                                    // p
+    double* vv = dots;                                    // v
     for (int k = 0; k + 2 < J; ++k) {
         const int m = J - k - 1;
-        double part = 0.0;
-        for (int i = 1 + tid; i < m; i += kEigThreads) {
-            double xi = A[(size_t)(k + 1 + i) * J + k];
-            part += xi * xi;
+        const double* x = A + (size_t)k * J + (k + 1);  // row k, columns k+1.. (= column k)
+        // w = A22 x (A22 is symmetric: read column i so a wave's loads are contiguous)
+        {
+            double acc = 0.0;
+            if (mi < m) {
+#pragma unroll 8
+                for (int j = mc; j < m; j += C) acc += A[(size_t)(k + 1 + j) * J + (k + 1 + mi)] * x[j];
+            }
+            part[mc * rb + mi] = acc;
         }
-        const double sigma = block_sum(part, red);
-        const double x0 = A[(size_t)(k + 1) * J + k];
-        const double dk = A[(size_t)k * J + k];
+        double sq = 0.0;
+        for (int j = 1 + lane; j < m; j += 64) sq += x[j] * x[j];
+        const double sigma = wave_sum(sq);  // same bits in every wave
+        const double x0 = x[0];
         double b, mu, v0;
         if (sigma == 0.0) {
             b = 0.0;
@@ -107,108 +205,121 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a) {
             v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
             b = 2.0 * v0 * v0 / (sigma + v0 * v0);
         }
+        const double inv_v0 = 1.0 / v0;
         if (tid == 0) {
-            d[k] = dk;
+            d[k] = A[(size_t)k * J + k];
             e[k] = mu;
             beta[k] = b;
         }
-        for (int i = tid; i < m; i += kEigThreads)
-            vb[i] = (i == 0) ? 1.0 : A[(size_t)(k + 1 + i) * J + k] / v0;
         __syncthreads();
         if (b != 0.0) {
-            // p = b * A22 v, one wave per row
-            for (int i = wave; i < m; i += kEigWaves) {
-                const double* row = A + (size_t)(k + 1 + i) * J + (k + 1);
-                double s = 0.0;
-                for (int j = lane; j < m; j += 64) s += row[j] * vb[j];
-                s = wave_sum(s);
-                if (lane == 0) pw[i] = b * s;
-            }
-            __syncthreads();
-            part = 0.0;
-            for (int i = tid; i < m; i += kEigThreads) part += pw[i] * vb[i];
-            const double kc = 0.5 * b * block_sum(part, red);
-            // A22 -= v w^T + w v^T with w = p - kc v
-            for (int i = wave; i < m; i += kEigWaves) {
-                const double vi = vb[i], wi = pw[i] - kc * vb[i];
-                double* row = A + (size_t)(k + 1 + i) * J + (k + 1);
-                for (int j = lane; j < m; j += 64) {
-                    const double wj = pw[j] - kc * vb[j];
-                    row[j] -= vi * wj + wi * vb[j];
+            // v = (x - mu e_1) / v0, so p = b A22 v = b (A22 x - mu A22 e_1) / v0;
+            // A22 e_1 is row 0 of A22.  Every wave forms kc = b/2 p.v from the
+            // partials itself (same order, same bits).
+            const double* a0 = A + (size_t)(k + 1) * J + (k + 1);
+            double pv = 0.0;
+            for (int j = lane; j < m; j += 64) {
+                double wj = 0.0;
+#pragma unroll 8
+                for (int c = 0; c < C; ++c) wj += part[c * rb + j];
+                const double pj = b * (wj - mu * a0[j]) * inv_v0;
+                const double vj = j == 0 ? 1.0 : x[j] * inv_v0;
+                pv += pj * vj;
+                if (wave == 0) {
+                    pp[j] = pj;
+                    vv[j] = vj;
                 }
             }
+            const double kc2 = b * wave_sum(pv);  // 2 kc
+            __syncthreads();
+            // A22 -= v p^T + p v^T - 2 kc v v^T, in a commutative form so that
+            // A stays exactly symmetric
+#pragma unroll 4
+            for (int i = wave; i < m; i += kEigWaves) {
+                const double vi = vv[i], pi = pp[i];
+                double* row = A + (size_t)(k + 1 + i) * J + (k + 1);
+                for (int j = lane; j < m; j += 64) {
+                    const double vj = vv[j], pj = pp[j];
+                    const double t = __dadd_rn(__dmul_rn(vi, pj), __dmul_rn(pi, vj));
+                    row[j] -= __dsub_rn(t, __dmul_rn(kc2, __dmul_rn(vi, vj)));
+                }
+            }
+            // the reflector goes below the diagonal of column k (no longer read)
+            for (int j = tid; j < m; j += kEigThreads) A[(size_t)(k + 1 + j) * J + k] = vv[j];
         }
-        __syncthreads();
-        for (int i = tid; i < m; i += kEigThreads) A[(size_t)(k + 1 + i) * J + k] = vb[i];
         __syncthreads();
     }
     if (tid == 0) {
         if (J >= 2) {
             d[J - 2] = A[(size_t)(J - 2) * J + (J - 2)];
-            e[J - 2] = A[(size_t)(J - 1) * J + (J - 2)];
+            e[J - 2] = A[(size_t)(J - 2) * J + (J - 1)];
             beta[J - 2] = 0.0;
         }
         d[J - 1] = A[(size_t)(J - 1) * J + (J - 1)];
         e[J - 1] = 0.0;
         beta[J - 1] = 0.0;
     }
+    // reflectors to global scratch: the LDS region is reused from step 4 on
+    for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) {
+        const int k = idx / J, i = idx - k * J;
+        if (i < J - k - 1) H[idx] = A[(size_t)(k + 1 + i) * J + k];
+    }
     __syncthreads();
-    for (int i = tid; i < J; i += kEigThreads) e2[i] = e[i] * e[i];
-    // Gershgorin interval and pivot floor
     if (tid == 0) {
-        double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
+        double gl = DBL_MAX, gu = -DBL_MAX;
         for (int i = 0; i < J; ++i) {
             double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < J ? fabs(e[i]) : 0.0);
             gl = fmin(gl, d[i] - r);
             gu = fmax(gu, d[i] + r);
-            if (i + 1 < J) emax2 = fmax(emax2, e[i] * e[i]);
         }
-        double tnorm = fmax(fabs(gl), fabs(gu));
+        const double tnorm = fmax(fabs(gl), fabs(gu));
+        // scale T by a power of two so that |entries| <= 1 (exact)
+        int ex = 0;
+        frexp(tnorm > 0.0 ? tnorm : 1.0, &ex);
+        const double sc = ldexp(1.0, -ex);
         // widen slightly so that count(gl) = 0 and count(gu) = J hold exactly
-        gl -= 2.0 * DBL_EPSILON * tnorm * J + 2.0 * DBL_MIN;
-        gu += 2.0 * DBL_EPSILON * tnorm * J + 2.0 * DBL_MIN;
-        red[32] = gl;
-        red[33] = gu;
-        red[34] = DBL_MIN * fmax(1.0, emax2);  // pivmin
+        red[32] = (gl - 2.0 * DBL_EPSILON * tnorm * J) * sc - 0x1p-900;
+        red[33] = (gu + 2.0 * DBL_EPSILON * tnorm * J) * sc + 0x1p-900;
+        red[34] = sc;
         red[35] = tnorm;
     }
     __syncthreads();
-    const double gl = red[32], gu = red[33], pivmin = red[34], tnorm = red[35];
+    const double sc = red[34], tnorm = red[35];
+    double* ds = dots;  // scaled diagonal
+    for (int i = tid; i < J; i += kEigThreads) {
+        ds[i] = d[i] * sc;
+        e2[i] = (e[i] * sc) * (e[i] * sc);
+    }
+    __syncthreads();
 
     // ---- 2. eigenvalues by multisection ---------------------------------
     {
+        const double gl = red[32], gu = red[33];
         int jp = 32;
         while (jp < J) jp *= 2;
-        const int tpe = kEigThreads / jp;  // threads per eigenvalue, <= 32
+        // about 256 active lanes (one wave per SIMD): more sample points per
+        // eigenvalue add work faster than they remove iterations
+        const int tpe = jp >= 256 ? 1 : 256 / jp;  // threads (sample points) per eigenvalue
         const int k = tid / tpe, s = tid - (tid / tpe) * tpe;
-        const int gofs = (lane / tpe) * tpe;  // group's first lane within the wave
-        const uint64_t gmask = (tpe == 64) ? ~0ull : (((1ull << tpe) - 1ull) << gofs);
-        const double atol = 2.0 * DBL_EPSILON * tnorm + 4.0 * pivmin;
+        const int gofs = (lane / tpe) * tpe;
+        const uint64_t gmask = (((1ull << tpe) - 1ull) << gofs);
+        (void)wave;
+        const double atol = 2.0 * DBL_EPSILON;  // T is scaled to norm <= 1
         double lo = gl, hi = gu;
         if (k < J) {
-            for (int it = 0; it < 128; ++it) {
+            for (int it = 0; it < 160; ++it) {
                 const double tol = fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
                 if (hi - lo <= tol) break;
-                const double x = lo + (hi - lo) * (double)(s + 1) / (double)(tpe + 1);
-                int c = 0;
-                double q = d[0] - x;
-                if (fabs(q) < pivmin) q = -pivmin;
-                c += q < 0.0;
-                for (int i = 1; i < J; ++i) {
-                    q = (d[i] - x) - e2[i - 1] / q;
-                    if (fabs(q) < pivmin) q = -pivmin;
-                    c += q < 0.0;
-                }
+                const double h = (hi - lo) / (double)(tpe + 1);
+                const int c = sturm_count(ds, e2, J, lo + h * (double)(s + 1));
                 const uint64_t bal = __ballot(c > k) & gmask;
-                const int sstar = bal ? (__ffsll((long long)bal) - 1 - gofs) : tpe;
-                const double nlo =
-                    sstar == 0 ? lo : lo + (hi - lo) * (double)sstar / (double)(tpe + 1);
-                const double nhi =
-                    sstar == tpe ? hi : lo + (hi - lo) * (double)(sstar + 1) / (double)(tpe + 1);
+                const int sstar = bal ? (__ffsll((long long)bal) - gofs) : tpe + 1;  // 1-based point
+                const double nlo = sstar == 1 ? lo : lo + h * (double)(sstar - 1);
+                const double nhi = sstar == tpe + 1 ? hi : lo + h * (double)sstar;
                 lo = nlo;
                 hi = nhi;
             }
-            if (s == 0) lam[J - 1 - k] = 0.5 * (lo + hi);
+            if (s == 0) lam[J - 1 - k] = 0.5 * (lo + hi) / sc;
         }
     }
     __syncthreads();
@@ -248,155 +359,223 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a) {
     }
     __syncthreads();
     const int R = misc[0];
-    const double ortol = 1e-3 * tnorm;
 
-    // ---- 4. inverse iteration for the R leading eigenvectors -------------
+    // ---- 4. inverse iteration, batches of vectors held in LDS -----------
     const double tiny = DBL_EPSILON * tnorm + DBL_MIN;
-    if (tid < R) {
-        const int j = tid;
-        const double sg = shift[j];
-        // LU with partial pivoting of T - sg I; arrays strided by J per row
-        double ai = d[0] - sg, bi = (J > 1) ? e[0] : 0.0;
-        for (int i = 0; i + 1 < J; ++i) {
-            const double ci = e[i];                 // sub-diagonal below row i
-            const double an = d[i + 1] - sg;        // next diagonal
-            const double bn = (i + 2 < J) ? e[i + 1] : 0.0;
-            if (fabs(ai) >= fabs(ci)) {
-                double piv = ai;
-                if (fabs(piv) < tiny) piv = (piv < 0.0 ? -tiny : tiny);
-                const double l = ci / piv;
-                U0[(size_t)i * J + j] = piv;
-                U1[(size_t)i * J + j] = bi;
-                U2[(size_t)i * J + j] = 0.0;
-                Lm[(size_t)i * J + j] = l;
-                PV[(size_t)i * J + j] = 0.0;
-                ai = an - l * bi;
-                bi = bn;
-            } else {
-                const double l = ai / ci;
-                U0[(size_t)i * J + j] = ci;
-                U1[(size_t)i * J + j] = an;
-                U2[(size_t)i * J + j] = bn;
-                Lm[(size_t)i * J + j] = l;
-                PV[(size_t)i * J + j] = 1.0;
-                ai = bi - l * an;
-                bi = -l * bn;
-            }
-        }
-        if (fabs(ai) < tiny) ai = (ai < 0.0 ? -tiny : tiny);
-        U0[(size_t)(J - 1) * J + j] = ai;
-        for (int i = 0; i < J; ++i) X[(size_t)i * J + j] = hash_unit((uint32_t)j, (uint32_t)i);
-    }
-    for (int it = 0; it < kInvIters; ++it) {
-        if (tid < R) {
-            const int j = tid;
-            // forward: apply the row interchanges and multipliers
+    const int batch = (int)((size_t)region / ((size_t)kLuArrays * J));
+    for (int j0 = 0; j0 < R; j0 += batch) {
+        const int nb = min(batch, R - j0);
+        // per-vector arrays, element i of vector jj at [array][i][jj]
+        double* RU0 = reg;
+        double* U1 = RU0 + (size_t)J * nb;
+        double* U2 = U1 + (size_t)J * nb;
+        double* LM = U2 + (size_t)J * nb;
+        double* PV = LM + (size_t)J * nb;
+        double* XV = PV + (size_t)J * nb;
+        __syncthreads();  // the region is free (A or the previous batch)
+        if (tid < nb) {
+            const int jj = tid, j = j0 + tid;
+            const double sg = shift[j];
+            double ai = d[0] - sg, bi = (J > 1) ? e[0] : 0.0;
             for (int i = 0; i + 1 < J; ++i) {
-                double xi = X[(size_t)i * J + j], xn = X[(size_t)(i + 1) * J + j];
-                if (PV[(size_t)i * J + j] != 0.0) {
-                    double t = xi;
-                    xi = xn;
-                    xn = t;
+                const double ci = e[i];
+                const double an = d[i + 1] - sg;
+                const double bn = (i + 2 < J) ? e[i + 1] : 0.0;
+                double u1, u2, l, pf, rp;
+                if (fabs(ai) >= fabs(ci)) {
+                    double piv = ai;
+                    u1 = bi;
+                    u2 = 0.0;
+                    if (fabs(piv) < tiny) piv = (piv < 0.0 ? -tiny : tiny);
+                    rp = recip(piv);
+                    l = ci * rp;
+                    pf = 0.0;
+                    ai = an - l * bi;
+                    bi = bn;
+                } else {
+                    double piv = ci;  // |ci| > |ai| >= 0
+                    u1 = an;
+                    u2 = bn;
+                    rp = recip(piv);
+                    l = ai * rp;
+                    pf = 1.0;
+                    ai = bi - l * an;
+                    bi = -l * bn;
+                    if (fabs(piv) < tiny) rp = recip(piv < 0.0 ? -tiny : tiny);
                 }
-                X[(size_t)i * J + j] = xi;
-                X[(size_t)(i + 1) * J + j] = xn - Lm[(size_t)i * J + j] * xi;
+                RU0[i * nb + jj] = rp;
+                U1[i * nb + jj] = u1;
+                U2[i * nb + jj] = u2;
+                LM[i * nb + jj] = l;
+                PV[i * nb + jj] = pf;
             }
-            // backward substitution with the three upper diagonals
-            double x1 = 0.0, x2 = 0.0, amax = 0.0;
-            for (int i = J - 1; i >= 0; --i) {
-                double v = X[(size_t)i * J + j];
-                if (i + 1 < J) v -= U1[(size_t)i * J + j] * x1;
-                if (i + 2 < J) v -= U2[(size_t)i * J + j] * x2;
-                v /= U0[(size_t)i * J + j];
-                X[(size_t)i * J + j] = v;
-                x2 = x1;
-                x1 = v;
-                amax = fmax(amax, fabs(v));
+            if (fabs(ai) < tiny) ai = (ai < 0.0 ? -tiny : tiny);
+            RU0[(J - 1) * nb + jj] = recip(ai);
+#pragma unroll 4
+            for (int i = 0; i < J; ++i) XV[i * nb + jj] = hash_unit((uint32_t)j, (uint32_t)i);
+            for (int it = 0; it < kInvIters; ++it) {
+                // forward: row interchanges and multipliers, running value in xc
+                double xc = XV[jj];
+#pragma unroll 4
+                for (int i = 0; i + 1 < J; ++i) {
+                    double xn = XV[(i + 1) * nb + jj];
+                    if (PV[i * nb + jj] != 0.0) {
+                        const double t = xc;
+                        xc = xn;
+                        xn = t;
+                    }
+                    XV[i * nb + jj] = xc;
+                    xc = xn - LM[i * nb + jj] * xc;
+                }
+                XV[(J - 1) * nb + jj] = xc;
+                // backward substitution
+                double x1 = 0.0, x2 = 0.0, amax = 0.0;
+#pragma unroll 4
+                for (int i = J - 1; i >= 0; --i) {
+                    double v = XV[i * nb + jj];
+                    v = fma(-U1[i * nb + jj], x1, v);
+                    v = fma(-U2[i * nb + jj], x2, v);
+                    v *= RU0[i * nb + jj];
+                    XV[i * nb + jj] = v;
+                    x2 = x1;
+                    x1 = v;
+                    amax = fmax(amax, fabs(v));
+                }
+                double nrm2 = 0.0;
+                const double scl = amax > 0.0 ? 1.0 / amax : 1.0;
+#pragma unroll 8
+                for (int i = 0; i < J; ++i) {
+                    const double v = XV[i * nb + jj] * scl;
+                    XV[i * nb + jj] = v;
+                    nrm2 += v * v;
+                }
+                const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+#pragma unroll 8
+                for (int i = 0; i < J; ++i) XV[i * nb + jj] *= inv;
             }
-            // normalise (scale by the max first to avoid overflow)
-            double nrm2 = 0.0;
-            const double sc = amax > 0.0 ? 1.0 / amax : 1.0;
-            for (int i = 0; i < J; ++i) {
-                double v = X[(size_t)i * J + j] * sc;
-                X[(size_t)i * J + j] = v;
-                nrm2 += v * v;
-            }
-            const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-            for (int i = 0; i < J; ++i) X[(size_t)i * J + j] *= inv;
         }
         __syncthreads();
-        // modified Gram-Schmidt inside clusters, in descending order
+        for (int idx = tid; idx < J * nb; idx += kEigThreads) {
+            const int jj = idx / J, i = idx - jj * J;
+            X[(size_t)(j0 + jj) * J + i] = XV[i * nb + jj];
+        }
+    }
+    __syncthreads();
+
+    // modified Gram-Schmidt, twice, inside clusters (descending order), by
+    // wave 0 with the working vectors in registers
+    const int nslot = (J + 63) / 64;
+    const double ortol = 1e-3 * tnorm;
+    if (wave == 0) {
         for (int j = 1; j < R; ++j) {
             int c0 = j;
             while (c0 > 0 && lam[c0 - 1] - lam[c0] <= ortol) --c0;
-            if (c0 == j) continue;  // uniform: every thread reads the same lam
+            if (c0 == j) continue;
+            double xj[kMaxVecSlots];
+#pragma unroll
+            for (int q = 0; q < kMaxVecSlots; ++q) {
+                const int t = lane + 64 * q;
+                xj[q] = (q < nslot && t < J) ? X[(size_t)j * J + t] : 0.0;
+            }
             for (int pass = 0; pass < 2; ++pass) {
-                for (int i = c0 + wave; i < j; i += kEigWaves) {
+                for (int i = c0; i < j; ++i) {
+                    double xi[kMaxVecSlots];
                     double s = 0.0;
-                    for (int t = lane; t < J; t += 64) s += X[(size_t)t * J + i] * X[(size_t)t * J + j];
+#pragma unroll
+                    for (int q = 0; q < kMaxVecSlots; ++q) {
+                        const int t = lane + 64 * q;
+                        xi[q] = (q < nslot && t < J) ? X[(size_t)i * J + t] : 0.0;
+                        s += xi[q] * xj[q];
+                    }
                     s = wave_sum(s);
-                    if (lane == 0) dots[i] = s;
+#pragma unroll
+                    for (int q = 0; q < kMaxVecSlots; ++q) xj[q] -= s * xi[q];
                 }
-                __syncthreads();
-                for (int t = tid; t < J; t += kEigThreads) {
-                    double v = X[(size_t)t * J + j];
-                    for (int i = c0; i < j; ++i) v -= dots[i] * X[(size_t)t * J + i];
-                    X[(size_t)t * J + j] = v;
-                }
-                __syncthreads();
             }
-            double part = 0.0;
-            for (int t = tid; t < J; t += kEigThreads) {
-                double v = X[(size_t)t * J + j];
-                part += v * v;
-            }
-            const double n2 = block_sum(part, red);
+            double n2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kMaxVecSlots; ++q) n2 += xj[q] * xj[q];
+            n2 = wave_sum(n2);
             const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-            for (int t = tid; t < J; t += kEigThreads) X[(size_t)t * J + j] *= inv;
-            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kMaxVecSlots; ++q) {
+                const int t = lane + 64 * q;
+                if (q < nslot && t < J) X[(size_t)j * J + t] = xj[q] * inv;
+            }
+            __threadfence_block();  // later iterations of this wave read column j
         }
     }
+    __syncthreads();
 
-    // ---- 5. back-transformation X <- Q X and the sign rule ---------------
-    if (tid < R) {
-        const int j = tid;
+    // ---- 5. back-transformation X <- Q X, Q = H_0 H_1 ... H_{J-3} -------
+    for (int j = wave; j < R; j += kEigWaves) {
+        double xr[kMaxVecSlots];
+#pragma unroll
+        for (int q = 0; q < kMaxVecSlots; ++q) {
+            const int t = lane + 64 * q;
+            xr[q] = (q < nslot && t < J) ? X[(size_t)j * J + t] : 0.0;
+        }
         for (int k = J - 3; k >= 0; --k) {
             const double b = beta[k];
-            if (b == 0.0) continue;
-            const int m = J - k - 1;
+            if (b == 0.0) continue;  // uniform
+            double hv[kMaxVecSlots];
             double s = 0.0;
-            for (int i = 0; i < m; ++i) s += A[(size_t)(k + 1 + i) * J + k] * X[(size_t)(k + 1 + i) * J + j];
-            s *= b;
-            for (int i = 0; i < m; ++i)
-                X[(size_t)(k + 1 + i) * J + j] -= s * A[(size_t)(k + 1 + i) * J + k];
+#pragma unroll
+            for (int q = 0; q < kMaxVecSlots; ++q) {
+                const int t = lane + 64 * q;
+                hv[q] = (q < nslot && t > k && t < J) ? H[(size_t)k * J + (t - k - 1)] : 0.0;
+                s += hv[q] * xr[q];
+            }
+            s = b * wave_sum(s);
+#pragma unroll
+            for (int q = 0; q < kMaxVecSlots; ++q) xr[q] -= s * hv[q];
         }
-        int best = 0;
-        double bv = fabs(X[j]);
-        for (int i = 1; i < J; ++i) {
-            double v = fabs(X[(size_t)i * J + j]);
-            if (v > bv) {
-                bv = v;
-                best = i;
+        // sign rule: the largest |entry| (lowest index on ties) is positive
+        double bv = -1.0;
+        int bi = J;
+#pragma unroll
+        for (int q = 0; q < kMaxVecSlots; ++q) {
+            const int t = lane + 64 * q;
+            if (q < nslot && t < J && fabs(xr[q]) > bv) {
+                bv = fabs(xr[q]);
+                bi = t;
             }
         }
-        const double sgn = X[(size_t)best * J + j] < 0.0 ? -1.0 : 1.0;
-        for (int i = 0; i < J; ++i) a.u[i + (size_t)J * j] = sgn * X[(size_t)i * J + j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        double at = 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxVecSlots; ++q)
+            if (lane + 64 * q == bi) at = xr[q];
+        const double sgn = wave_sum(at) < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < kMaxVecSlots; ++q) {
+            const int t = lane + 64 * q;
+            if (q < nslot && t < J) X[(size_t)j * J + t] = sgn * xr[q];
+        }
     }
 }
 
 int launch_eig(const EigArgs& a, hipStream_t st) {
-    const size_t small = (size_t)(10 * a.J + 64) * sizeof(double) + 64;
+    const int region = (int)eig_region_doubles(a.J);
+    const size_t lds = ((size_t)region + eig_small_doubles(a.J)) * sizeof(double);
     if (a.J <= 128) {
-        size_t lds = (size_t)a.J * a.J * sizeof(double) + small;
         auto fn = eig_kernel<true>;
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a);
+        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
     } else {
         auto fn = eig_kernel<false>;
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)small));
-        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), small, st, a);
+                                   (int)lds));
+        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
     }
     TK_HIP(hipGetLastError());
     return TK_OK;

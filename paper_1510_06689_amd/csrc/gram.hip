@@ -2,14 +2,19 @@
 // computed in the natural layout without permuting data (Sec. V-C, local
 // part), exploiting symmetry: only 16x16 blocks (bi <= bj) are formed.
 //
-// Stage 1 (gram_partial_*): workgroup (p, g) streams its contiguous range of
-// column tiles (TileMap) through LDS and accumulates the block pairs of pair
-// group g in registers; it writes one partial per pair to the workspace.
+// Stage 1 (gram_partial_f64): workgroup (p, g) streams its contiguous range
+// of column tiles (TileMap) through a double-buffered LDS tile and
+// accumulates the block pairs of pair group g in registers.  Each wave owns
+// NPW block pairs (a compile-time count, so the MFMA loop is branch-free)
+// and a k-slice of each tile.  One barrier per tile: while the MFMAs read
+// buffer t % 2 the registers holding tile t + 1 are written to the other
+// buffer.  It writes one partial per pair to the workspace.
 // Stage 2 (gram_reduce): sums the partials over p in a fixed order (so S is
 // bitwise reproducible) and mirrors the upper blocks into both triangles.
 //
 // FP64 path: v_mfma_f64_16x16x4f64 on FP64 data (FP32 input is widened
 // exactly while staging).
+#include "tile_io.hpp"
 #include "tk_common.hpp"
 
 namespace tk {
@@ -18,7 +23,6 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kGramThreads = 512;
 constexpr int kGramWaves = kGramThreads / 64;
-constexpr int kGramMaxPairs = 8;  // 16x16 block pairs held per wave (FP64)
 
 // Pair index p -> (bi, bj), upper-triangle blocks in row-major order.
 __device__ __forceinline__ void pair_of(int p, int nb, int& bi, int& bj) {
@@ -32,180 +36,138 @@ __device__ __forceinline__ void pair_of(int p, int nb, int& bi, int& bj) {
     bj = row + (p - start);
 }
 
-template <typename T>
-__device__ __forceinline__ double widen(T v) { return (double)v; }
+// LDS doubles: two [JB][KT + 1] tile buffers (at least the area used to fold
+// k-slices at the end).
+template <int JB, int KT, int NPW>
+constexpr int kGramLdsDoubles = 2 * JB * (KT + 1) > kGramWaves * NPW * 256
+                                    ? 2 * JB * (KT + 1)
+                                    : kGramWaves * NPW * 256;
 
-// Loads this thread's share of one column tile into registers.  The tile is
-// J x KT (rows padded to JB); element e = tid + kGramThreads * q is mapped so
-// that consecutive threads read consecutive memory.  Masked elements are 0.
-template <typename T, int JB, int KT>
-struct TileLoader {
-    static constexpr int kElems = JB * KT;
-    static constexpr int kPer = (kElems + kGramThreads - 1) / kGramThreads;
-    double v[kPer];
-
-    __device__ __forceinline__ void load(const T* __restrict__ y, const TileMap& tm,
-                                         const Tile& t, int tid) {
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            int e = tid + kGramThreads * q;
-            double val = 0.0;
-            if (tm.packed) {
-                if (e < t.nvalid) val = widen(y[t.base + e]);
-            } else {
-                int i = e / KT, kk = e - (e / KT) * KT;
-                if (i < tm.J && kk < t.ncols) val = widen(y[t.base + (int64_t)i * tm.L + kk]);
-            }
-            v[q] = val;
-        }
-    }
-
-    // LDS layout: [row i][column kk] with pitch KT + 1 doubles.
-    __device__ __forceinline__ void store(double* lds, const TileMap& tm, const Tile& t,
-                                          int tid) const {
-        constexpr int P = KT + 1;
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            int e = tid + kGramThreads * q;
-            if (tm.packed) {
-                // memory order [bb][i][l]; column kk = bb * L + l
-                int L = (int)tm.L;
-                int JL = tm.J * L;
-                int bb = e / JL;
-                int rem = e - bb * JL;
-                int i = rem / L;
-                int l = rem - i * L;
-                if (bb < tm.nbb) lds[i * P + bb * L + l] = v[q];
-            } else {
-                int i = e / KT, kk = e - (e / KT) * KT;
-                if (i < JB) lds[i * P + kk] = v[q];
-            }
-        }
-    }
-};
-
-// LDS doubles: the [JB][KT + 1] tile, at least the [waves][256] area used to
-// fold k-slices at the end.
-template <int JB, int KT>
-constexpr int kGramLdsDoubles =
-    JB * (KT + 1) > kGramWaves * 256 ? JB * (KT + 1) : kGramWaves * 256;
-
-template <typename T, int JB, int KT>
+// NPW: block pairs per wave; KS: waves sharing one pair set, each taking
+// every KS-th k-step.  The waves form kGramWaves / KS groups of NPW pairs.
+template <typename T, int JB, int KT, int NPW, int KS>
 __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
     const T* __restrict__ y, TileMap tm, int nb, int npairs, int pairs_per_group,
     double* __restrict__ partial) {
     extern __shared__ double lds[];
     constexpr int P = KT + 1;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+    constexpr int NG = kGramWaves / KS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
 
-    // zero the whole tile area once; padded rows J..JB-1 stay zero
-    for (int e = tid; e < kGramLdsDoubles<JB, KT>; e += kGramThreads) lds[e] = 0.0;
+    for (int e = tid; e < 2 * JB * P; e += kGramThreads) lds[e] = 0.0;
 
-    // this group's pairs and this wave's assignment
     const int g0 = blockIdx.y * pairs_per_group;
     const int npg = min(npairs - g0, pairs_per_group);
-    int kslices = 1, slice = 0, first = wave, stride = kGramWaves, mine = 0;
-    if (npg < kGramWaves) {
-        kslices = kGramWaves / npg;
-        slice = wave / npg;
-        first = wave % npg;
-        stride = npg;
-        mine = (wave < npg * kslices) ? 1 : 0;
-    } else {
-        mine = (npg - wave + kGramWaves - 1) / kGramWaves;
-    }
-    int bi[kGramMaxPairs], bj[kGramMaxPairs];
+    const int grp = wave % NG, slice = wave / NG;
+    int aoff[NPW], boff[NPW];
 #pragma unroll
-    for (int q = 0; q < kGramMaxPairs; ++q) {
-        bi[q] = 0;
-        bj[q] = 0;
-        if (q < mine) pair_of(g0 + first + q * stride, nb, bi[q], bj[q]);
+    for (int q = 0; q < NPW; ++q) {
+        int p = g0 + min(grp * NPW + q, npg - 1);  // spare slots repeat the last pair
+        int bi, bj;
+        pair_of(p, nb, bi, bj);
+        aoff[q] = (bi * 16 + r16) * P + k4;
+        boff[q] = (bj * 16 + r16) * P + k4;
     }
-    d4_t acc[kGramMaxPairs];
+    d4_t acc[NPW];
 #pragma unroll
-    for (int q = 0; q < kGramMaxPairs; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NPW; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
 
     const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
     const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
 
-    TileLoader<T, JB, KT> ld;
-    Tile cur{};
-    if (t0 < t1) {
-        cur = tile_at(tm, t0, tm.J);
-        ld.load(y, tm, cur, tid);
-    }
-    const int r16 = lane & 15;
-    const int k4 = lane >> 4;
+    ColumnTile<T, double, JB, KT, kGramThreads> ld;
+    ld.setup(tm, tid);
+    if (t0 < t1) ld.load(y, tm, tile_at(tm, t0, tm.J));
+    __syncthreads();  // zeroing done before the first store
+    if (t0 < t1) ld.store(lds);
+    __syncthreads();
     for (int64_t t = t0; t < t1; ++t) {
-        __syncthreads();  // previous tile fully consumed
-        ld.store(lds, tm, cur, tid);
-        __syncthreads();
-        if (t + 1 < t1) {
-            cur = tile_at(tm, t + 1, tm.J);
-            ld.load(y, tm, cur, tid);  // in flight while the MFMAs run
-        }
-#pragma unroll 2
-        for (int ks = slice; ks < KT / 4; ks += kslices) {
-            const int col = ks * 4 + k4;
+        const double* cur = lds + ((t - t0) & 1) * (JB * P);
+        double* nxt = lds + (((t - t0) + 1) & 1) * (JB * P);
+        const bool more = t + 1 < t1;
+        if (more) ld.load(y, tm, tile_at(tm, t + 1, tm.J));  // in flight during the MFMAs
 #pragma unroll
-            for (int q = 0; q < kGramMaxPairs; ++q) {
-                if (q < mine) {
-                    double a = lds[(bi[q] * 16 + r16) * P + col];
-                    double b = lds[(bj[q] * 16 + r16) * P + col];
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
-                }
+        for (int kq = 0; kq < KT / 4 / KS; ++kq) {
+            const int ks = kq * KS + slice;
+            double a[NPW], b[NPW];
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) {
+                a[q] = cur[aoff[q] + ks * 4];
+                b[q] = cur[boff[q] + ks * 4];
             }
+#pragma unroll
+            for (int q = 0; q < NPW; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
         }
+        if (more) ld.store(nxt);
+        __syncthreads();
     }
 
-    // combine k-slices (fixed order), then write one partial per pair.
     // v_mfma_f64_16x16x4f64 leaves D[row][col] in lane col + 16 * (row % 4),
     // register row / 4, i.e. row = 4 * v + lane / 16, col = lane % 16.
     double* out = partial + (int64_t)blockIdx.x * npairs * 256;
-    if (kslices > 1) {
-        __syncthreads();
-        double* red = lds;  // [wave][256]
-        if (mine) {
+    if constexpr (KS > 1) {
+        double* red = lds;  // [wave][NPW][256]
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * v + k4) * 16 + r16] = acc[0][v];
-        }
+        for (int q = 0; q < NPW; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                red[(wave * NPW + q) * 256 + (4 * v + k4) * 16 + r16] = acc[q][v];
         __syncthreads();
-        if (mine && slice == 0) {
-            for (int e = lane; e < 256; e += 64) {
-                double s = 0.0;
-                for (int sl = 0; sl < kslices; ++sl) s += red[(sl * npg + first) * 256 + e];
-                out[(int64_t)(g0 + first) * 256 + e] = s;
+        if (slice == 0) {
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) {
+                int pl = grp * NPW + q;
+                if (pl < npg) {
+                    for (int e = lane; e < 256; e += 64) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int sl = 0; sl < KS; ++sl)
+                            s += red[((sl * NG + grp) * NPW + q) * 256 + e];
+                        out[(int64_t)(g0 + pl) * 256 + e] = s;
+                    }
+                }
             }
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < kGramMaxPairs; ++q) {
-            if (q < mine) {
-                int p = g0 + first + q * stride;
+        for (int q = 0; q < NPW; ++q) {
+            int pl = grp * NPW + q;
+            if (pl < npg) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) out[(int64_t)p * 256 + (4 * v + k4) * 16 + r16] = acc[q][v];
+                for (int v = 0; v < 4; ++v)
+                    out[(int64_t)(g0 + pl) * 256 + (4 * v + k4) * 16 + r16] = acc[q][v];
             }
         }
     }
 }
 
-// S[r + J c] for the upper block pairs, summed over the P partials in order.
-__global__ void gram_reduce(const double* __restrict__ partial, int P, int npairs, int nb, int J,
-                            double* __restrict__ s) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= npairs * 256) return;
+// S[r + J c] for the upper block pairs.  Each workgroup reduces 64 outputs;
+// its 4 wave-sized groups sum the partials p = g, g + 4, ... and the four
+// group sums are added in a fixed order.
+__global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ partial, int P,
+                                                   int npairs, int nb, int J,
+                                                   double* __restrict__ s) {
+    __shared__ double part[4][64];
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + o;
+    const int n = npairs * 256;
+    double acc = 0.0;
+    if (idx < n)
+        for (int q = g; q < P; q += 4) acc += partial[(int64_t)q * n + idx];
+    part[g][o] = acc;
+    __syncthreads();
+    if (g != 0 || idx >= n) return;
+    const double tot = ((part[0][o] + part[1][o]) + part[2][o]) + part[3][o];
     int p = idx >> 8, e = idx & 255;
     int bi, bj;
     pair_of(p, nb, bi, bj);
     int r = bi * 16 + (e >> 4), c = bj * 16 + (e & 15);
     if (r >= J || c >= J) return;
     if (bi == bj && r > c) return;  // diagonal blocks: upper triangle only, then mirror
-    double acc = 0.0;
-    for (int q = 0; q < P; ++q) acc += partial[(int64_t)q * npairs * 256 + idx];
-    s[r + (int64_t)J * c] = acc;
-    s[c + (int64_t)J * r] = acc;
+    s[r + (int64_t)J * c] = tot;
+    s[c + (int64_t)J * r] = tot;
 }
 
 // trace(S) = ||Y||^2, summed in a fixed order by one wave.
@@ -231,20 +193,43 @@ static int round_jb(int J) {
     return jb;
 }
 
+// Static schedule per padded extent: tile width, pairs per wave, k-slices
+// per pair set, and pairs per workgroup group.
+struct GramShape {
+    int KT, NPW, KS, per_group;
+};
+
+template <int JB>
+constexpr GramShape gram_shape() {
+    return JB == 32    ? GramShape{32, 1, 2, 4}    //   3 pairs: 4 groups x 1, 2 k-slices
+           : JB == 64  ? GramShape{32, 3, 2, 12}   //  10 pairs: 4 groups x 3, 2 k-slices
+           : JB == 128 ? GramShape{32, 5, 1, 40}   //  36 pairs: 8 waves x 5
+           : JB == 256 ? GramShape{32, 6, 1, 48}   // 136 pairs: 3 groups of <= 48
+                       : GramShape{16, 8, 1, 64};  // 528 pairs: 9 groups of <= 64
+}
+
+static GramShape gram_shape_rt(int jb) {
+    switch (jb) {
+        case 32: return gram_shape<32>();
+        case 64: return gram_shape<64>();
+        case 128: return gram_shape<128>();
+        case 256: return gram_shape<256>();
+        default: return gram_shape<512>();
+    }
+}
+
 GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
-    (void)precision;
     (void)elem_bytes;
+    if (precision == TK_GRAM_SPLIT_BF16) return plan_gram_mixed(v);
     GramPlan pl{};
-    int jb = round_jb(v.J);
-    pl.KT = jb >= 512 ? 16 : 32;
+    GramShape gs = gram_shape_rt(round_jb(v.J));
+    pl.KT = gs.KT;
     pl.nb = (v.J + 15) / 16;
     pl.npairs = pl.nb * (pl.nb + 1) / 2;
-    int per_group = kGramWaves * kGramMaxPairs;
-    pl.G = (pl.npairs + per_group - 1) / per_group;
+    pl.G = (pl.npairs + gs.per_group - 1) / gs.per_group;
     pl.pairs_per_group = (pl.npairs + pl.G - 1) / pl.G;
     TileMap tm = make_tiles(v, pl.KT);
-    int cus = device_cu_count();
-    int64_t want = (int64_t)2 * cus / pl.G;
+    int64_t want = (int64_t)2 * device_cu_count() / pl.G;
     if (want < 1) want = 1;
     pl.P = (int)(tm.ntiles < want ? tm.ntiles : want);
     if (pl.P < 1) pl.P = 1;
@@ -252,11 +237,12 @@ GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
     return pl;
 }
 
-template <typename T, int JB, int KT>
+template <typename T, int JB>
 static int launch_partial(const T* y, const TileMap& tm, const GramPlan& pl, double* partial,
                           hipStream_t st) {
-    size_t lds = (size_t)kGramLdsDoubles<JB, KT> * sizeof(double);
-    auto fn = gram_partial_f64<T, JB, KT>;
+    constexpr GramShape gs = gram_shape<JB>();
+    size_t lds = (size_t)kGramLdsDoubles<JB, gs.KT, gs.NPW> * sizeof(double);
+    auto fn = gram_partial_f64<T, JB, gs.KT, gs.NPW, gs.KS>;
     TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     hipLaunchKernelGGL(fn, dim3(pl.P, pl.G), dim3(kGramThreads), lds, st, y, tm, pl.nb, pl.npairs,
@@ -269,39 +255,39 @@ template <typename T>
 static int dispatch_partial(const T* y, const ModeView& v, const GramPlan& pl, double* partial,
                             hipStream_t st) {
     TileMap tm = make_tiles(v, pl.KT);
-    int jb = round_jb(v.J);
-    switch (jb) {
-        case 32: return launch_partial<T, 32, 32>(y, tm, pl, partial, st);
-        case 64: return launch_partial<T, 64, 32>(y, tm, pl, partial, st);
-        case 128: return launch_partial<T, 128, 32>(y, tm, pl, partial, st);
-        case 256: return launch_partial<T, 256, 32>(y, tm, pl, partial, st);
-        case 512: return launch_partial<T, 512, 16>(y, tm, pl, partial, st);
+    switch (round_jb(v.J)) {
+        case 32: return launch_partial<T, 32>(y, tm, pl, partial, st);
+        case 64: return launch_partial<T, 64>(y, tm, pl, partial, st);
+        case 128: return launch_partial<T, 128>(y, tm, pl, partial, st);
+        case 256: return launch_partial<T, 256>(y, tm, pl, partial, st);
+        case 512: return launch_partial<T, 512>(y, tm, pl, partial, st);
         default: return fail(TK_ERR_UNSUPPORTED, "mode extent %d exceeds %d", v.J, TK_MAX_MODE_DIM);
     }
 }
 
-int launch_gram_mixed(const float* y, const ModeView& v, double* s, void* ws, size_t ws_bytes,
-                      hipStream_t st);
+int launch_gram_reduce(const double* partial, const GramPlan& pl, int J, double* s,
+                       hipStream_t st) {
+    int n = pl.npairs * 256;
+    hipLaunchKernelGGL(gram_reduce, dim3((n + 63) / 64), dim3(256), 0, st, partial, pl.P,
+                       pl.npairs, pl.nb, J, s);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
 
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
                 double* sumsq, void* ws, size_t ws_bytes, hipStream_t st) {
+    GramPlan pl = plan_gram(v, precision, (int)dtype_size(dtype));
+    if (ws_bytes < pl.partial_bytes)
+        return fail(TK_ERR_WORKSPACE, "gram workspace %zu < %zu", ws_bytes, pl.partial_bytes);
+    double* partial = (double*)ws;
     if (precision == TK_GRAM_SPLIT_BF16) {
-        TK_TRY(launch_gram_mixed((const float*)y, v, s, ws, ws_bytes, st));
+        TK_TRY(launch_gram_mixed((const float*)y, v, pl, partial, st));
+    } else if (dtype == TK_F64) {
+        TK_TRY(dispatch_partial((const double*)y, v, pl, partial, st));
     } else {
-        GramPlan pl = plan_gram(v, precision, (int)dtype_size(dtype));
-        if (ws_bytes < pl.partial_bytes)
-            return fail(TK_ERR_WORKSPACE, "gram workspace %zu < %zu", ws_bytes, pl.partial_bytes);
-        double* partial = (double*)ws;
-        if (dtype == TK_F64) {
-            TK_TRY(dispatch_partial((const double*)y, v, pl, partial, st));
-        } else {
-            TK_TRY(dispatch_partial((const float*)y, v, pl, partial, st));
-        }
-        int n = pl.npairs * 256;
-        hipLaunchKernelGGL(gram_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partial, pl.P,
-                           pl.npairs, pl.nb, v.J, s);
-        TK_HIP(hipGetLastError());
+        TK_TRY(dispatch_partial((const float*)y, v, pl, partial, st));
     }
+    TK_TRY(launch_gram_reduce(partial, pl, v.J, s, st));
     if (sumsq) {
         hipLaunchKernelGGL(gram_trace, dim3(1), dim3(64), 0, st, s, v.J, sumsq);
         TK_HIP(hipGetLastError());

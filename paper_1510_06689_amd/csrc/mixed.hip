@@ -3,9 +3,15 @@
 
 namespace tk {
 
-int launch_gram_mixed(const float* y, const ModeView& v, double* s, void* ws, size_t ws_bytes,
+GramPlan plan_gram_mixed(const ModeView& v) {
+    (void)v;
+    GramPlan pl{};
+    return pl;
+}
+
+int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
                       hipStream_t st) {
-    (void)y; (void)v; (void)s; (void)ws; (void)ws_bytes; (void)st;
+    (void)y; (void)v; (void)pl; (void)partial; (void)st;
     return fail(TK_ERR_UNSUPPORTED, "split-bf16 Gram not built");
 }
 

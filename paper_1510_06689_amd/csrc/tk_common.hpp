@@ -147,6 +147,9 @@ struct GramPlan {
     size_t partial_bytes;
 };
 GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes);
+GramPlan plan_gram_mixed(const ModeView& v);
+int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
+                      hipStream_t st);
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
                 double* sumsq, void* ws, size_t ws_bytes, hipStream_t st);
 
