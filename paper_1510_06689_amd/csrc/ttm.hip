@@ -131,23 +131,21 @@ static int launch_ttm_t(const T* y, const ModeView& v, const double* m, int64_t 
     TileMap tm = make_tiles(v, KT);
     size_t lds = (size_t)JB * ((KT + 1) + (KB + 1)) * sizeof(double);
     int G = (K + KB - 1) / KB;
-    int64_t want = (int64_t)device_cu_count() / G;
+    auto fn = v.L < 16 ? ttm_f64_kernel<T, JB, KB, KT, true> : ttm_f64_kernel<T, JB, KB, KT, false>;
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    // One wave of resident workgroups: as many per CU as registers and LDS
+    // allow, each streaming a contiguous range of tiles.
+    int per_cu = 1;
+    TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kTtmThreads,
+                                                        lds));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+    int64_t want = (int64_t)per_cu * device_cu_count() / G;
     if (want < 1) want = 1;
     int P = (int)(tm.ntiles < want ? tm.ntiles : want);
     if (P < 1) return TK_OK;
-    if (v.L < 16) {
-        auto fn = ttm_f64_kernel<T, JB, KB, KT, true>;
-        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL(fn, dim3(P, G), dim3(kTtmThreads), lds, st, y, tm, m, ldm, K,
-                           transpose, z);
-    } else {
-        auto fn = ttm_f64_kernel<T, JB, KB, KT, false>;
-        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL(fn, dim3(P, G), dim3(kTtmThreads), lds, st, y, tm, m, ldm, K,
-                           transpose, z);
-    }
+    hipLaunchKernelGGL(fn, dim3(P, G), dim3(kTtmThreads), lds, st, y, tm, m, ldm, K, transpose,
+                       z);
     TK_HIP(hipGetLastError());
     return TK_OK;
 }
