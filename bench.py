@@ -1,15 +1,19 @@
 """ST-HOSVD throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--path both|mixed|fp64]
 
 A step is one full ST-HOSVD (Alg. 1: every mode's Gram, FP64 eigensolve,
 rank rule and TTM) of the combustion-shaped 128x128x128x32x32 tensor
 (planted ranks (16,16,16,8,8), spectra decaying by 0.7, cosine factors,
 noise 1e-5), eps = 1e-4, modes in order 1..5, with the tensor resident in
-HBM.  The timed region is exactly K steps bracketed by device
-synchronisation.  Prints one JSON line with the input throughput (GB/s of
-input tensor per second), the roofline of the dominant kernel (the mode-1
-Gram), and the CPU oracle timed on a bounded slab of the same tensor.
+HBM.  Two legs, each timed over exactly K steps bracketed by device
+synchronisation: the FP64 path on the FP64 tensor and the mixed path
+(split-bf16 Gram, split-bf16 TTM, FP64 eigensolve) on the same tensor
+stored FP32.  The headline value is the mixed leg's input throughput (GB/s
+of stored input per second); the line also carries the FP64 leg, the
+speedup, both legs' ranks and relative errors, the mode-1 Gram/TTM rates,
+the roofline of the dominant kernel (the mode-1 Gram) and the CPU oracle
+timed on a bounded slab of the same tensor.
 """
 from __future__ import annotations
 
@@ -70,10 +74,10 @@ def time_gram(x, mode, precision, reps, stream):
 
 
 def cpu_baseline(x_dev, eps, path):
-    """The FP64 CPU oracle on one time-step slab of the same tensor."""
+    """The FP64 CPU oracle on a three-time-step slab of the same tensor."""
     import oracle
     import numpy as np
-    sample = x_dev[..., 0:1]
+    sample = x_dev[..., 0:3]
     xs = np.asfortranarray(sample.double().cpu().numpy())
     t0 = time.perf_counter()
     oracle.sthosvd(xs, eps)
@@ -81,8 +85,73 @@ def cpu_baseline(x_dev, eps, path):
     in_bytes = xs.size * x_dev.element_size()
     return {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one time step of the same tensor, dims {list(xs.shape)}, "
-                      f"{path} input bytes {in_bytes}, {dt:.1f} s single-threaded"}
+            "sample": f"three time steps of the same tensor, dims {list(xs.shape)}, "
+                      f"{in_bytes} bytes as stored on the {path} path, {dt:.1f} s "
+                      f"single-threaded"}
+
+
+def time_ttm(x, mode, u, precision, reps, stream):
+    """Average duration of one ttm_mode_n launch (Y x_n U^T) on the stream."""
+    import ctypes
+    lib = tucker.library()
+    sh = tucker.shape_of(x)
+    dims = list(x.shape)
+    dims[mode] = u.shape[1]
+    z = tucker.empty_fortran(dims, x.dtype, x.device)
+    args = (ctypes.byref(sh), x.data_ptr(), mode, u.data_ptr(), u.shape[0], u.shape[1], 1,
+            tucker.TTM_PRECISIONS[precision], z.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+    tucker._check(lib.ttm_mode_n(*args))
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(reps):
+            tucker._check(lib.ttm_mode_n(*args))
+        end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps, z.numel() * z.element_size()
+
+
+def run_leg(name, x, w, gp, tp, steps, warmup):
+    """Warm up, then time exactly `steps` ST-HOSVDs bracketed by device syncs."""
+    dev = x.device
+    comp = tucker.Compressor(w.dims, x.dtype, dev, w.eps, gram_precision=gp, ttm_precision=tp)
+    for i in range(warmup):
+        comp.run(x)
+        log(f"[{name}] warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        comp.run(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / steps * 1e3
+    res = comp.result()
+    xh = tucker.reconstruct(res.core, res.factors, precision="fp64")
+    e2, mx, n2 = tucker.error_metrics(x, xh)
+    del xh, comp
+    torch.cuda.empty_cache()
+    in_bytes = x.numel() * x.element_size()
+    leg = {"ms_per_step": round(ms, 4), "input_gbs": round(in_bytes / (ms / 1e3) / 1e9, 2),
+           "gelem_s": round(x.numel() / (ms / 1e3) / 1e9, 3), "ranks": list(res.ranks),
+           "relerr": math.sqrt(e2 / n2), "max_abs_err": mx, "gram": gp, "ttm": tp,
+           "storage": str(x.dtype).replace("torch.", "")}
+    log(f"[{name}] {steps} steps: {ms:.3f} ms/step, {leg['input_gbs']} GB/s, ranks {res.ranks},"
+        f" relerr {leg['relerr']:.3e}")
+    return leg, res
+
+
+def kernel_rates(x, res, gp, tp, reps, stream):
+    """Mode-1 Gram and TTM of a leg, each timed alone with HIP events on the
+    library's stream: algorithmic TFLOP/s and GB/s."""
+    j, r = x.shape[0], res.ranks[0]
+    tg = time_gram(x, 0, gp, reps, stream)
+    tt, zbytes = time_ttm(x, 0, res.factors[0], tp, reps, stream)
+    b = x.numel() * x.element_size()
+    return {"gram_ms": round(tg * 1e3, 4), "gram_tflops": round(gram_flops(j, x.numel()) / tg / 1e12, 3),
+            "gram_gbs": round(b / tg / 1e9, 1),
+            "ttm_ms": round(tt * 1e3, 4), "ttm_tflops": round(2.0 * r * x.numel() / tt / 1e12, 3),
+            "ttm_gbs": round((b + zbytes) / tt / 1e9, 1)}
 
 
 def main():
@@ -90,7 +159,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--path", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--path", choices=["both", "fp64", "mixed"], default="both",
+                    help="both: the mixed path is the headline, the FP64 path its reference")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gram-reps", type=int, default=10)
     args = ap.parse_args()
@@ -102,72 +172,73 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
-    w = synth.WORKLOADS["combustion128"]
-    dtype = torch.float64 if args.path == "fp64" else torch.float32
-    gp, tp = ("fp64", "fp64") if args.path == "fp64" else ("split_bf16", "bf16x3")
-    log(f"generating {w.name} {w.dims} on {dev}")
-    x = w.make(dtype=dtype, device=dev)
-    torch.cuda.synchronize()
-    comp = tucker.Compressor(w.dims, dtype, dev, w.eps, gram_precision=gp, ttm_precision=tp)
     stream = torch.cuda.current_stream(dev)
+    w = synth.WORKLOADS["combustion128"]
+    log(f"generating {w.name} {w.dims} on {dev}")
+    x64 = w.make(dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
 
-    for i in range(args.warmup):
-        comp.run(x)
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        comp.run(x)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
+    legs, kern = {}, {}
+    if args.path in ("both", "fp64"):
+        legs["fp64"], res64 = run_leg("fp64", x64, w, "fp64", "fp64", args.steps, args.warmup)
+        kern["fp64"] = kernel_rates(x64, res64, "fp64", "fp64", args.gram_reps, stream)
+        log(f"[fp64] mode-1 kernels {kern['fp64']}")
+    x32 = None
+    if args.path in ("both", "mixed"):
+        x32 = tucker.empty_fortran(w.dims, torch.float32, dev)
+        x32.copy_(x64)  # the same tensor rounded to FP32 (nearest even)
+        if args.path == "mixed":
+            del x64
+            x64 = None
+            torch.cuda.empty_cache()
+        legs["mixed"], resm = run_leg("mixed", x32, w, "split_bf16", "bf16x3", args.steps,
+                                      args.warmup)
+        kern["mixed"] = kernel_rates(x32, resm, "split_bf16", "bf16x3", args.gram_reps, stream)
+        log(f"[mixed] mode-1 kernels {kern['mixed']}")
+
+    head = "mixed" if "mixed" in legs else "fp64"
+    x = x32 if head == "mixed" else x64
+    leg, k = legs[head], kern[head]
     in_bytes = x.numel() * x.element_size()
-    value = in_bytes / (ms / 1e3) / 1e9
-    res = comp.result()
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step, {value:.1f} GB/s, ranks {res.ranks}")
-
-    # accuracy of the timed configuration (untimed)
-    xh = tucker.reconstruct(res.core, res.factors, precision="fp64")
-    e2, mx, n2 = tucker.error_metrics(x, xh)
-    relerr = math.sqrt(e2 / n2)
-    del xh
-    torch.cuda.empty_cache()
-
-    # roofline of the dominant kernel: the mode-1 Gram
-    tg = time_gram(x, 0, gp, args.gram_reps, stream)
-    flops = gram_flops(w.dims[0], x.numel())
-    if args.path == "fp64":
-        achieved = flops / tg / 1e12
+    if head == "mixed":
+        achieved = in_bytes / (k["gram_ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "gram_partial_bf16s (mode 1, J=128, FP32 input)",
+                "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": k["gram_ms"]}
+    else:
+        flops = gram_flops(w.dims[0], x.numel())
+        achieved = flops / (k["gram_ms"] / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFS, 4),
                 "traffic": None, "kernel": "gram_partial_f64 (mode 1, J=128)",
-                "gram_ms": round(tg * 1e3, 4), "algorithmic_flops": flops}
-    else:
-        achieved = in_bytes / tg / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "gram_partial_split_bf16 (mode 1, J=128)",
-                "gram_ms": round(tg * 1e3, 4), "algorithmic_bytes": in_bytes}
-    log(f"mode-1 gram: {tg * 1e3:.3f} ms")
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": k["gram_ms"]}
 
     out = {
         "metric": "ST-HOSVD input GB/s + Gram/TTM TFLOP/s, mixed vs FP64 GPU at rel err <=1e-4",
-        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "value": leg["input_gbs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.path == "fp64" else "bf16-split/f32/f64",
+        "dtype": "bf16x3/f32/f64" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "combustion128: 128x128x128x32x32 planted Tucker, ranks "
-                               "(16,16,16,8,8), decay 0.7, noise 1e-5, eps 1e-4, order 1..5",
-                   "dims": list(w.dims), "eps": w.eps, "path": args.path,
-                   "storage": str(dtype).replace("torch.", ""),
-                   "gram": gp, "ttm": tp},
-        "ranks": list(res.ranks), "relerr": relerr, "max_abs_err": mx,
+                               "(16,16,16,8,8), decay 0.7, cosine factors, noise 1e-5, "
+                               "eps 1e-4, modes 1..5" +
+                               (", stored FP32 (mixed path)" if head == "mixed" else ", FP64"),
+                   "dims": list(w.dims), "eps": w.eps, "headline": head},
+        "legs": legs, "mode1_kernels": kern,
         "roofline": roof,
     }
+    if "fp64" in legs and "mixed" in legs:
+        out["speedup_mixed_vs_fp64"] = round(legs["fp64"]["ms_per_step"] /
+                                             legs["mixed"]["ms_per_step"], 3)
+        out["accuracy"] = {
+            "ranks_equal": legs["fp64"]["ranks"] == legs["mixed"]["ranks"],
+            "relerr_fp64": legs["fp64"]["relerr"], "relerr_mixed": legs["mixed"]["relerr"],
+            "abs_delta": abs(legs["fp64"]["relerr"] - legs["mixed"]["relerr"])}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(x, w.eps, args.path)
+        out["cpu_baseline"] = cpu_baseline(x, w.eps, head)
     print(json.dumps(out), flush=True)
 
 

@@ -74,10 +74,16 @@ typedef enum tk_gram_precision {
     /* FP64 products and FP64 accumulation on FP64 matrix cores (FP32 input is
      * widened exactly). */
     TK_GRAM_FP64 = 0,
-    /* FP32 input only: each value x is split into bf16 hi = rne(x) and
-     * lo = rne(x - hi); the four products hh, hl, lh, ll run on bf16 matrix
-     * cores with FP32 accumulation over short chunks that are flushed into
-     * FP64 accumulators. */
+    /* FP32 input only.  Per column tile and row i with max |x| < 2^E_i, each
+     * value is split as hi = round(x 2^(7-E_i)) (an integer, exact in bf16)
+     * and lo = bf16(x 2^(7-E_i) - hi); the four products hh, hl, lh, ll run
+     * on bf16 matrix cores.  hh is summed exactly in FP32, the other three in
+     * a second FP32 accumulator; both are scaled by 2^(E_i+E_j-14) and added
+     * into FP64 after every tile.  Each element is represented to 2^-16 of
+     * its row's maximum.  In sthosvd_compress a rank found from such a Gram
+     * is accepted only when the eps threshold lies clear of the tail sums on
+     * both sides by a margin of 2^-27 trace R (J - R) / J^2; otherwise that
+     * mode's Gram is recomputed in FP64 (tk_tucker.fp64_modes). */
     TK_GRAM_SPLIT_BF16 = 1
 } tk_gram_precision;
 
@@ -85,7 +91,9 @@ typedef enum tk_gram_precision {
 typedef enum tk_ttm_precision {
     TK_TTM_FP64 = 0,   /* FP64 products and accumulation (FP64 or FP32 storage) */
     TK_TTM_BF16 = 1,   /* FP32 storage: operands rounded to bf16, FP32 accumulation */
-    TK_TTM_BF16X3 = 2  /* FP32 storage: split bf16, products hh + hl + lh, FP32 accumulation */
+    TK_TTM_BF16X3 = 2  /* FP32 storage: hi = bf16(x), lo = bf16(x - hi) on both operands,
+                          products hh + hl + lh, FP32 accumulation (relative error ~2^-17);
+                          see tk_tucker.ttm_precision_used for its use in sthosvd_compress */
 } tk_ttm_precision;
 
 /* Shape and element type of a dense tensor (dims[0] fastest in memory). */
@@ -155,6 +163,13 @@ typedef struct tk_tucker {
     int64_t ranks[TK_MAX_NDIM];        /* R_n */
     double discarded[TK_MAX_NDIM];     /* sum_{r > R_n} lambda_r at mode n */
     double norm2;                      /* ||X||^2 */
+    uint32_t fp64_modes;               /* bit n: mode n's Gram was recomputed in FP64 because
+                                          the split-bf16 Gram could not certify its rank
+                                          (gram_precision TK_GRAM_SPLIT_BF16 only) */
+    int32_t ttm_precision_used;        /* tk_ttm_precision the TTMs ran in: TK_TTM_BF16X3
+                                          becomes TK_TTM_FP64 under the eps rule when
+                                          eps^2 / N < 2^-31, where its 2^-17 relative output
+                                          error would reach the rank threshold */
 } tk_tucker;
 
 /*

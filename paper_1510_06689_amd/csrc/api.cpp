@@ -225,9 +225,15 @@ static int check_options(const tk_shape* x, const tk_options* opt, SthosvdPlan* 
     for (int s = 0; s < N; ++s) {
         int n = pl->order[s];
         ModeView v = mode_view(cur, N, n);
+        // the tile count (hence the partial count) depends on the ranks found
+        // at run time, so size for the grid cap of this mode's extent
         GramPlan gp = plan_gram(v, opt->gram_precision, (int)b);
-        size_t gb = gp.partial_bytes;
+        size_t gb = gp.partial_bound;
         if (gb > pl->gram_bytes) pl->gram_bytes = gb;
+        if (opt->gram_precision != TK_GRAM_FP64) {  // room for the guard's FP64 Gram
+            GramPlan g64 = plan_gram(v, TK_GRAM_FP64, (int)b);
+            if (g64.partial_bound > pl->gram_bytes) pl->gram_bytes = g64.partial_bound;
+        }
         if (v.J > jmax) jmax = v.J;
         cur[n] = pl->cap[n];
         if (s + 1 < N) {
@@ -302,6 +308,10 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     for (int k = 0; k < N; ++k) cur[k] = x->dims[k];
     const void* ycur = x_dev;
     const double eps2n = opt->eps * opt->eps / (double)N;
+    uint32_t fp64_modes = 0;
+    int ttm_prec = opt->ttm_precision;
+    if (ttm_prec == TK_TTM_BF16X3 && !opt->fixed_ranks && eps2n < kSplitTtmFloor)
+        ttm_prec = TK_TTM_FP64;
     double nu_host = 0.0;
 
     for (int s = 0; s < N; ++s) {
@@ -322,6 +332,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         ea.disc_out = disc_dev + n;
         ea.flags = flags_dev;
         ea.scratch = eig_ws;
+        const bool mixed = opt->gram_precision != TK_GRAM_FP64;
+        ea.guard = (mixed && !opt->fixed_ranks) ? kSplitGramGuard : 0.0;
         TK_TRY(launch_eig(ea, st));
 
         int64_t R;
@@ -336,6 +348,20 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
             TK_HIP(hipMemcpyAsync(hbuf, nu_dev, sizeof(double), hipMemcpyDeviceToHost, st));
             TK_HIP(hipMemcpyAsync(&flags, flags_dev, sizeof(int), hipMemcpyDeviceToHost, st));
             TK_HIP(hipStreamSynchronize(st));
+            if (flags & 4) {
+                // the mixed Gram cannot certify this rank: redo the mode in FP64
+                TK_HIP(hipMemsetAsync(flags_dev, 0, sizeof(int), st));
+                TK_TRY(launch_gram(ycur, x->dtype, v, TK_GRAM_FP64, S, s == 0 ? nu_dev : nullptr,
+                                   gram_ws, pl.gram_bytes, st));
+                ea.guard = 0.0;
+                TK_TRY(launch_eig(ea, st));
+                TK_HIP(hipMemcpyAsync(&rk, rank_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                      st));
+                TK_HIP(hipMemcpyAsync(hbuf, nu_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+                TK_HIP(hipMemcpyAsync(&flags, flags_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+                TK_HIP(hipStreamSynchronize(st));
+                fp64_modes |= 1u << n;
+            }
             nu_host = hbuf[0];
             if (!std::isfinite(nu_host))
                 return fail(TK_ERR_NONFINITE, "sthosvd_compress: input holds Inf or NaN");
@@ -358,8 +384,7 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         } else {
             dst = ybuf[s & 1];
         }
-        TK_TRY(launch_ttm(ycur, x->dtype, v, out->factors_dev[n], R, v.J, 1,
-                          opt->ttm_precision, dst, st));
+        TK_TRY(launch_ttm(ycur, x->dtype, v, out->factors_dev[n], R, v.J, 1, ttm_prec, dst, st));
         memcpy(cur, nxt, sizeof cur);
         ycur = dst;
     }
@@ -377,6 +402,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         out->discarded[n] = disc[n];
     }
     out->norm2 = nu_host;
+    out->fp64_modes = fp64_modes;
+    out->ttm_precision_used = ttm_prec;
     return TK_OK;
 }
 

@@ -339,6 +339,17 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
                 tail += fmax(lam[R - 1], 0.0);
                 --R;
             }
+            if (a.guard > 0.0) {
+                // the decision must survive the Gram's error in the tail
+                // sums: tau - t_R and t_{R-1} - tau both beyond the margin
+                double tr = 0.0;
+                for (int r = J - 1; r >= 0; --r) tr += fmax(lam[r], 0.0);
+                const double margin = a.guard * tr * (double)R * (double)(J - R) /
+                                      ((double)J * (double)J);
+                const double next = tail + fmax(lam[R - 1], 0.0);
+                if (tau - tail < margin || (R > 1 && next - tau < margin))
+                    a.flags[0] |= 4;
+            }
         }
         int flag = 0;
         if (R > a.max_rank) {
@@ -411,6 +422,10 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
             }
             if (fabs(ai) < tiny) ai = (ai < 0.0 ? -tiny : tiny);
             RU0[(J - 1) * nb + jj] = recip(ai);
+            // the last row has no superdiagonal terms; back substitution
+            // reads them (times zero), so they must not be stale LDS
+            U1[(J - 1) * nb + jj] = 0.0;
+            U2[(J - 1) * nb + jj] = 0.0;
 #pragma unroll 4
             for (int i = 0; i < J; ++i) XV[i * nb + jj] = hash_unit((uint32_t)j, (uint32_t)i);
             for (int it = 0; it < kInvIters; ++it) {

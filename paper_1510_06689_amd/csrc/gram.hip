@@ -234,6 +234,7 @@ GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
     pl.P = (int)(tm.ntiles < want ? tm.ntiles : want);
     if (pl.P < 1) pl.P = 1;
     pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
+    pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
     return pl;
 }
 

@@ -1,25 +1,608 @@
-// Mixed-precision (split-bf16) Gram and bf16 TTM kernels.
+// Mixed-precision kernels for FP32-stored tensors: the split-bf16 Gram and
+// the bf16 / split-bf16 TTM.  Neither changes what Alg. 1 computes; they
+// change the arithmetic of its two bulk steps (Gram, TTM) while the
+// eigendecomposition and the rank rule stay in FP64.
+//
+// Split-bf16 Gram.  The rank rule compares tail sums of eigenvalues with
+// eps^2 ||X||^2 / N, so the Gram's error in the trailing eigenvalues must
+// stay far below that threshold.  Two error sources would not: rounding the
+// running hi*hi sums in FP32, and dropping lo*lo, which off the diagonal is
+// a sum of uncorrelated rounding residues that does not average out of the
+// trailing eigenvalues.  Hence, per tile of KT columns and per row i with
+// max |x| < 2^E_i:
+//     hi = round(x 2^(7 - E_i))           an integer in [-128, 128], exact in bf16
+//     lo = bf16(x 2^(7 - E_i) - hi)       the scaled residual, |lo| <= 1/2
+// and a 32x32 block of S = Y_(n) Y_(n)^T is
+//     2^(E_i + E_j - 14) (H_i H_j^T + [H_i L_j^T + L_i H_j^T + L_i L_j^T])
+// on v_mfma_f32_32x32x16_bf16.  H H^T sums at most 128 products of
+// magnitude <= 2^14 per tile, so its FP32 accumulator is exact; the bracket
+// is at most 2^-7 of it and keeps its own FP32 accumulator.  Both are scaled
+// and added into FP64 registers after every tile.  What remains is the
+// bf16 rounding of lo (2^-17 of the row maximum), an error tied to each
+// element that enters the trailing eigenvalues only at second order.
+// Partials use the FP64 Gram's 16x16 pair layout and its fixed-order
+// reduction.
+//
+// bf16 TTM.  Z = op(M) Y with op(M) (K x J) split into bf16 hi/lo fragments
+// once per workgroup (in LDS) and Y split per element as it is loaded:
+// BF16 forms A_hi Y_hi; BF16X3 adds A_hi Y_lo + A_lo Y_hi
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation, FP32 output).  When the
+// columns are contiguous (mode 1) every lane loads its eight consecutive
+// rows straight from HBM, no LDS staging needed.
 #include "tk_common.hpp"
 
 namespace tk {
 
-GramPlan plan_gram_mixed(const ModeView& v) {
-    (void)v;
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f16_t __attribute__((ext_vector_type(16)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef int i4_t __attribute__((ext_vector_type(4)));
+
+// ================================================================== Gram
+
+constexpr int kMxThreads = 512;
+constexpr int kMxWaves = kMxThreads / 64;
+
+// Loader modes.
+enum { kUnit = 0, kContig = 1, kStrided = 2 };
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_max(unsigned v) {
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+    return o > v ? o : v;
+}
+
+// One J x KT tile of FP32 columns, held by the workgroup in registers as
+// groups of eight consecutive columns of one row, split as described above
+// and stored to LDS as two [JB][KT + 8] bf16 planes (a 16-byte row pad keeps
+// the 16-byte fragment reads and writes free of bank conflicts) plus the
+// JB row exponents.  Every row's groups sit in one wave, so the row maximum
+// is a reduction among a few lanes, with no barrier:
+//   kUnit    (L == 1): wave w owns rows [w RW, w RW + RW); lane l holds row
+//            l % RW, groups l / RW + m (64 / RW).  A load instruction reads
+//            RW consecutive rows (contiguous) of 64 / RW columns.
+//   kContig  (L % 8 == 0, 16-byte aligned): lane group of KT / 8 consecutive
+//            threads owns one row, thread t the column group t % (KT / 8);
+//            each group is two 16-byte loads.
+//   kStrided (otherwise): as kContig, one element per load.
+template <int JB, int KT, int MODE>
+struct SplitTile {
+    static constexpr int PK = KT + 8;
+    static constexpr int NCG = KT / 8;                              // groups per row
+    static constexpr int RW = JB / kMxWaves > 16 ? JB / kMxWaves : 16;  // kUnit rows per wave
+    static constexpr int LPR = 64 / RW;                             // kUnit lanes per row
+    static constexpr int ROWSTEP = kMxThreads / NCG;                // strided rows per pass
+    static constexpr int NGRP = MODE == kUnit ? NCG / LPR : JB * NCG / kMxThreads;
+    static_assert(RW <= 64 && NCG % LPR == 0, "unit mapping");
+    static_assert(MODE == kUnit || (NGRP >= 1 && JB * NCG % kMxThreads == 0 && NCG <= 16),
+                  "strided mapping");
+
+    float v[NGRP][8];
+    int i0, cg0;
+    bool owner;      // kUnit: this wave holds rows
+    int coff[8];     // strided: offsets of the thread's 8 columns inside a tile
+
+    __device__ static __forceinline__ int64_t col_offset(int kk, int64_t L, int J) {
+        const int64_t bb = kk / L;
+        return bb * J * L + (kk - bb * L);
+    }
+
+    __device__ __forceinline__ void setup(const TileMap& tm, int tid) {
+        if (MODE == kUnit) {
+            const int w = tid >> 6, l = tid & 63;
+            owner = w * RW < JB;
+            i0 = w * RW + l % RW;
+            cg0 = l / RW;
+        } else {
+            owner = true;
+            cg0 = tid % NCG;
+            i0 = tid / NCG;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) coff[e] = (int)col_offset(8 * cg0 + e, tm.L, tm.J);
+        }
+    }
+    __device__ __forceinline__ int row_of(int m) const {
+        return MODE == kUnit ? i0 : i0 + m * ROWSTEP;
+    }
+    __device__ __forceinline__ int cg_of(int m) const {
+        return MODE == kUnit ? cg0 + m * LPR : cg0;
+    }
+
+    __device__ __forceinline__ void load(const float* __restrict__ y, const TileMap& tm,
+                                         const Tile& t) {
+        const int J = tm.J;
+        if (MODE == kUnit) {
+            // element (i0, kk) with kk = 8 cg0 + [8 m LPR + e]: a wave-uniform
+            // column part plus a fixed per-lane 32-bit offset
+            const bool ok = owner && i0 < J;
+            const int loff = i0 + 8 * cg0 * J;
+#pragma unroll
+            for (int m = 0; m < NGRP; ++m) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int ku = 8 * m * LPR + e;
+                    const float* ub = y + t.base + (int64_t)ku * J;
+                    v[m][e] = (ok && 8 * cg0 + ku < t.ncols) ? ub[loff] : 0.f;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NGRP; ++m) {
+                const int i = row_of(m);
+                const int64_t rowbase = t.base + (int64_t)i * tm.L;
+                if (MODE == kContig && i < J && 8 * cg0 + 8 <= t.ncols) {
+                    const f4_t* p = (const f4_t*)(y + rowbase + coff[0]);
+                    const f4_t a = p[0], b = p[1];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        v[m][e] = a[e];
+                        v[m][4 + e] = b[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int kk = 8 * cg0 + e;
+                        v[m][e] = (i < J && kk < t.ncols) ? y[rowbase + coff[e]] : 0.f;
+                    }
+                }
+            }
+        }
+    }
+
+    // Largest |x| of the row of group m over the whole tile (as float bits).
+    __device__ __forceinline__ unsigned row_max_bits(int m) const {
+        unsigned b = 0;
+        if (MODE == kUnit) {
+#pragma unroll
+            for (int q = 0; q < NGRP; ++q)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const unsigned u = __float_as_uint(v[q][e]) & 0x7fffffffu;
+                    b = u > b ? u : b;
+                }
+#pragma unroll
+            for (int d = RW; d < 64; d *= 2) {
+                const unsigned o = (unsigned)__shfl_xor((int)b, d);
+                b = o > b ? o : b;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const unsigned u = __float_as_uint(v[m][e]) & 0x7fffffffu;
+                b = u > b ? u : b;
+            }
+            // max over the NCG (aligned, consecutive) lanes of the row
+            if (NCG >= 2) b = dpp_max<0xb1>(b);    // quad_perm [1,0,3,2]
+            if (NCG >= 4) b = dpp_max<0x4e>(b);    // quad_perm [2,3,0,1]
+            if (NCG >= 8) b = dpp_max<0x141>(b);   // row_half_mirror
+            if (NCG >= 16) b = dpp_max<0x140>(b);  // row_mirror
+        }
+        return b;
+    }
+
+    // Split and store the tile; the row exponents go next to the planes.
+    __device__ __forceinline__ void store(__bf16* hi, __bf16* lo, int* ex) {
+        unsigned mb = 0;
+        if (MODE == kUnit) mb = row_max_bits(0);  // every group of the thread is one row
+#pragma unroll
+        for (int m = 0; m < NGRP; ++m) {
+            if (MODE != kUnit) mb = row_max_bits(m);
+            // max |x| < 2^E; zero rows get the smallest normal exponent
+            const int E = (int)(mb >> 23) - 126;
+            const int sh = 7 - (E < -125 ? -125 : E);
+            bf8_t h, l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float sx = __builtin_ldexpf(v[m][e], sh);
+                const float d = __builtin_rintf(sx);
+                h[e] = (__bf16)d;
+                l[e] = (__bf16)(sx - d);
+            }
+            const int r = row_of(m);
+            if (MODE != kUnit || owner) {
+                const int off = r * PK + 8 * cg_of(m);
+                *(bf8_t*)(hi + off) = h;
+                *(bf8_t*)(lo + off) = l;
+                if (cg_of(m) == 0) ex[r] = 7 - sh;
+            }
+        }
+    }
+};
+
+// Pair index p -> (bi, bj), upper-triangle 32-blocks in row-major order.
+__device__ __forceinline__ void pair32_of(int p, int nb, int& bi, int& bj) {
+    int row = 0, start = 0;
+    while (p >= start + (nb - row)) {
+        start += nb - row;
+        ++row;
+    }
+    bi = row;
+    bj = row + (p - start);
+}
+
+// One LDS tile buffer: hi plane, lo plane (bf16 [JB][KT + 8]) and JB row
+// exponents; two buffers alternate.
+template <int JB, int KT>
+constexpr size_t mx_buf_bytes() {
+    return ((size_t)2 * JB * (KT + 8) * sizeof(__bf16) + (size_t)JB * sizeof(int) + 15) / 16 * 16;
+}
+
+// Every 32-block pair of the workgroup's pair group has one owner wave
+// (pair g0 + wave + 8 q, q < NPW), which sees every column of every tile, so
+// each output lives in exactly one wave's registers.
+template <int JB, int KT, int NPW, int MODE>
+__global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
+    const float* __restrict__ y, TileMap tm, int npairs32, int pairs_per_group, int npairs16,
+    double* __restrict__ partial) {
+    extern __shared__ double lds_raw[];
+    using Ld = SplitTile<JB, KT, MODE>;
+    constexpr int PK = Ld::PK;
+    constexpr int PLANE = JB * PK;
+    constexpr size_t BUF = mx_buf_bytes<JB, KT>();
+    constexpr int NKS = KT / 16;
+    constexpr int NB = JB / 32;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int g0 = blockIdx.y * pairs_per_group;
+
+    int bi[NPW], bj[NPW], aoff[NPW], boff[NPW];
+    bool act[NPW];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        const int pl = wave + q * kMxWaves;
+        const int p = g0 + pl;
+        act[q] = pl < pairs_per_group && p < npairs32;
+        pair32_of(act[q] ? p : 0, NB, bi[q], bj[q]);
+        aoff[q] = (32 * bi[q] + r32) * PK + 8 * kh;
+        boff[q] = (32 * bj[q] + r32) * PK + 8 * kh;
+    }
+
+    f16_t acch[NPW], accr[NPW];
+    double accd[NPW][16];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accd[q][v] = 0.0;
+    }
+
+    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    char* base = (char*)lds_raw;
+    auto hi_of = [&](int b) { return (__bf16*)(base + b * BUF); };
+    auto ex_of = [&](int b) { return (int*)(base + b * BUF + 2 * PLANE * sizeof(__bf16)); };
+
+    Ld ld;
+    ld.setup(tm, tid);
+    if (t0 < t1) {
+        ld.load(y, tm, tile_at(tm, t0, tm.J));
+        ld.store(hi_of(0), hi_of(0) + PLANE, ex_of(0));
+    }
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+        const int cur = (int)((t - t0) & 1);
+        const bool more = t + 1 < t1;
+        if (more) ld.load(y, tm, tile_at(tm, t + 1, tm.J));  // in flight during the MFMAs
+        const __bf16* hb = hi_of(cur);
+        const __bf16* lb = hb + PLANE;
+        const int* ex = ex_of(cur);
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            if (!act[q]) continue;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                acch[q][v] = 0.f;
+                accr[q][v] = 0.f;
+            }
+#pragma unroll 2
+            for (int ks = 0; ks < NKS; ++ks) {
+                const bf8_t ah = *(const bf8_t*)(hb + aoff[q] + 16 * ks);
+                const bf8_t al = *(const bf8_t*)(lb + aoff[q] + 16 * ks);
+                const bf8_t bh = *(const bf8_t*)(hb + boff[q] + 16 * ks);
+                const bf8_t bl = *(const bf8_t*)(lb + boff[q] + 16 * ks);
+                acch[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acch[q], 0, 0, 0);
+                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, accr[q], 0, 0, 0);
+                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, accr[q], 0, 0, 0);
+                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, accr[q], 0, 0, 0);
+            }
+            // v_mfma_f32_32x32x16: row (v / 4) * 8 + (lane / 32) * 4 + v % 4, column lane % 32
+            const int ej = ex[32 * bj[q] + r32] - 14;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const i4_t ei = *(const i4_t*)(ex + 32 * bi[q] + 8 * g + 4 * kh);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int v = 4 * g + c;
+                    const double sv = (double)acch[q][v] + (double)accr[q][v];
+                    accd[q][v] += __builtin_ldexp(sv, ei[c] + ej);
+                }
+            }
+        }
+        if (more) {
+            const int nb2 = cur ^ 1;
+            ld.store(hi_of(nb2), hi_of(nb2) + PLANE, ex_of(nb2));
+        }
+        __syncthreads();
+    }
+
+    double* out = partial + (int64_t)blockIdx.x * npairs16 * 256;
+    constexpr int NB16 = 2 * NB;
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        if (!act[q]) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = (v >> 2) * 8 + kh * 4 + (v & 3);
+            const int gi = 32 * bi[q] + row, gj = 32 * bj[q] + r32;
+            const int BI = gi >> 4, BJ = gj >> 4;
+            if (BI > BJ) continue;  // lower half of a diagonal 32-block
+            const int p16 = BI * NB16 - BI * (BI - 1) / 2 + (BJ - BI);
+            out[(int64_t)p16 * 256 + (gi & 15) * 16 + (gj & 15)] = accd[q][v];
+        }
+    }
+}
+
+// Static schedule per padded extent: tile width, pairs per wave, pair groups
+// (each re-reads the tensor), workgroups per CU.
+struct MxGramShape {
+    int KT, NPW, G, per_cu;
+};
+template <int JB>
+constexpr MxGramShape mx_gram_shape() {
+    return JB == 32    ? MxGramShape{128, 1, 1, 2}   //   1 pair
+           : JB == 64  ? MxGramShape{128, 1, 1, 2}   //   3 pairs
+           : JB == 128 ? MxGramShape{128, 2, 1, 1}   //  10 pairs over 8 waves
+           : JB == 256 ? MxGramShape{64, 2, 3, 1}    //  36 pairs: 3 groups of 12
+                       : MxGramShape{16, 2, 9, 1};   // 136 pairs: 9 groups of 16
+}
+
+static int mx_round_jb(int J) {
+    int jb = 32;
+    while (jb < J) jb *= 2;
+    return jb;
+}
+
+template <int JB>
+static GramPlan mx_plan(const ModeView& v) {
+    constexpr MxGramShape gs = mx_gram_shape<JB>();
+    static_assert(kMxWaves * gs.NPW * gs.G >= JB / 32 * (JB / 32 + 1) / 2 &&
+                      kMxWaves * gs.NPW >= (JB / 32 * (JB / 32 + 1) / 2 + gs.G - 1) / gs.G,
+                  "every pair of a group needs an owner wave");
     GramPlan pl{};
+    TileMap tm = make_tiles(v, gs.KT);
+    const int nb32 = JB / 32;
+    const int npairs32 = nb32 * (nb32 + 1) / 2;
+    pl.KT = gs.KT;
+    pl.G = gs.G;
+    pl.pairs_per_group = (npairs32 + gs.G - 1) / gs.G;
+    pl.nb = 2 * nb32;  // 16-blocks, for the shared reduction
+    pl.npairs = pl.nb * (pl.nb + 1) / 2;
+    int64_t want = (int64_t)gs.per_cu * device_cu_count() / pl.G;
+    if (want < 1) want = 1;
+    pl.P = (int)(tm.ntiles < want ? tm.ntiles : want);
+    if (pl.P < 1) pl.P = 1;
+    pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
+    pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
     return pl;
+}
+
+GramPlan plan_gram_mixed(const ModeView& v) {
+    switch (mx_round_jb(v.J)) {
+        case 32: return mx_plan<32>(v);
+        case 64: return mx_plan<64>(v);
+        case 128: return mx_plan<128>(v);
+        case 256: return mx_plan<256>(v);
+        default: return mx_plan<512>(v);
+    }
+}
+
+template <int JB, int MODE>
+static int mx_launch(const float* y, const TileMap& tm, const GramPlan& pl, double* partial,
+                     hipStream_t st) {
+    constexpr MxGramShape gs = mx_gram_shape<JB>();
+    auto fn = gram_partial_bf16s<JB, gs.KT, gs.NPW, MODE>;
+    const size_t lds = 2 * mx_buf_bytes<JB, gs.KT>();
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    const int nb32 = JB / 32;
+    hipLaunchKernelGGL(fn, dim3(pl.P, pl.G), dim3(kMxThreads), lds, st, y, tm,
+                       nb32 * (nb32 + 1) / 2, pl.pairs_per_group, pl.npairs, partial);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+template <int JB>
+static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& pl,
+                            double* partial, hipStream_t st) {
+    TileMap tm = make_tiles(v, pl.KT);
+    if (v.L == 1) return mx_launch<JB, kUnit>(y, tm, pl, partial, st);
+    const bool contig = v.L % 8 == 0 && ((uintptr_t)y & 15) == 0;
+    if (contig) return mx_launch<JB, kContig>(y, tm, pl, partial, st);
+    return mx_launch<JB, kStrided>(y, tm, pl, partial, st);
 }
 
 int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
                       hipStream_t st) {
-    (void)y; (void)v; (void)pl; (void)partial; (void)st;
-    return fail(TK_ERR_UNSUPPORTED, "split-bf16 Gram not built");
+    switch (mx_round_jb(v.J)) {
+        case 32: return mx_dispatch_mode<32>(y, v, pl, partial, st);
+        case 64: return mx_dispatch_mode<64>(y, v, pl, partial, st);
+        case 128: return mx_dispatch_mode<128>(y, v, pl, partial, st);
+        case 256: return mx_dispatch_mode<256>(y, v, pl, partial, st);
+        case 512: return mx_dispatch_mode<512>(y, v, pl, partial, st);
+        default: return fail(TK_ERR_UNSUPPORTED, "mode extent %d exceeds %d", v.J, TK_MAX_MODE_DIM);
+    }
+}
+
+// ================================================================== TTM
+
+constexpr int kMtThreads = 256;
+constexpr int kMtWaves = kMtThreads / 64;
+
+// NKB: 16-row blocks of op(M) per workgroup; NKS: 32-wide k-steps over J;
+// X3: split both operands (three products) instead of one bf16 product.
+// UNIT: columns contiguous (L == 1, J % 8 == 0), loaded as 16-byte vectors.
+template <int NKB, int NKS, bool X3, bool UNIT>
+__global__ __launch_bounds__(kMtThreads) void ttm_bf16_kernel(
+    const float* __restrict__ y, int64_t L, int64_t ncols, int J, const double* __restrict__ m,
+    int64_t ldm, int K, int transpose, float* __restrict__ z) {
+    __shared__ bf8_t afr[NKB * NKS * 2][64];  // [(kb * NKS + ks) * 2 + hi/lo][lane]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int r0 = blockIdx.y * NKB * 16;
+
+    // A fragments: lane l holds op(M)[r0 + 16 kb + l % 16][32 ks + 8 (l / 16) + e].
+    for (int f = tid; f < NKB * NKS * 64; f += kMtThreads) {
+        const int l = f & 63, kbks = f >> 6;
+        const int kb = kbks / NKS, ks = kbks - (kbks / NKS) * NKS;
+        const int r = r0 + 16 * kb + (l & 15);
+        bf8_t h, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = 32 * ks + 8 * (l >> 4) + e;
+            double a = 0.0;
+            if (r < K && j < J) a = transpose ? m[j + ldm * r] : m[r + ldm * j];
+            const float af = (float)a;
+            const __bf16 ah = (__bf16)af;
+            h[e] = ah;
+            lo[e] = (__bf16)(af - (float)ah);
+        }
+        afr[kbks * 2][l] = h;
+        afr[kbks * 2 + 1][l] = lo;
+    }
+    __syncthreads();
+
+    const int c16 = lane & 15, g4 = lane >> 4;
+    const int64_t nblk = (ncols + 15) / 16;
+    const int64_t wstride = (int64_t)gridDim.x * kMtWaves;
+    const int64_t JL = (int64_t)J * L, KL = (int64_t)K * L;
+    for (int64_t cb = (int64_t)blockIdx.x * kMtWaves + (tid >> 6); cb < nblk; cb += wstride) {
+        const int64_t col = cb * 16 + c16;
+        const bool cv = col < ncols;
+        int64_t b = 0, l = 0;
+        if (!UNIT) {
+            b = col / L;
+            l = col - b * L;
+        }
+        const float* ycol = UNIT ? y + col * J : y + b * JL + l;
+        f4_t acc[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) acc[kb] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const int j0 = 32 * ks + 8 * g4;
+            float x[8];
+            if (UNIT) {
+                if (cv && j0 < J) {
+                    const f4_t* p = (const f4_t*)(ycol + j0);
+                    const f4_t a = p[0], c = p[1];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        x[e] = a[e];
+                        x[4 + e] = c[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[e] = 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    x[e] = (cv && j0 + e < J) ? ycol[(int64_t)(j0 + e) * L] : 0.f;
+            }
+            bf8_t yh, yl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 h = (__bf16)x[e];
+                yh[e] = h;
+                if (X3) yl[e] = (__bf16)(x[e] - (float)h);
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                const bf8_t ah = afr[(kb * NKS + ks) * 2][lane];
+                acc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh, acc[kb], 0, 0, 0);
+                if (X3) {
+                    const bf8_t al = afr[(kb * NKS + ks) * 2 + 1][lane];
+                    acc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl, acc[kb], 0, 0, 0);
+                    acc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh, acc[kb], 0, 0, 0);
+                }
+            }
+        }
+        if (!cv) continue;
+        // v_mfma_f32_16x16x32: row 4 * (lane / 16) + v, column lane % 16
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            const int rb = r0 + 16 * kb + 4 * g4;
+            if (UNIT) {
+                float* zc = z + col * K;
+                if (rb + 4 <= K && (K & 3) == 0) {
+                    *(f4_t*)(zc + rb) = acc[kb];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (rb + v < K) zc[rb + v] = acc[kb][v];
+                }
+            } else {
+                float* zc = z + b * KL + l;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (rb + v < K) zc[(int64_t)(rb + v) * L] = acc[kb][v];
+            }
+        }
+    }
+}
+
+template <int NKB, int NKS, bool X3>
+static int mt_launch(const float* y, const ModeView& v, const double* m, int64_t ldm, int K,
+                     int transpose, float* z, hipStream_t st) {
+    const int64_t ncols = v.L * v.B;
+    const bool unit = v.L == 1 && v.J % 8 == 0 && ((uintptr_t)y & 15) == 0 &&
+                      ((uintptr_t)z & 15) == 0;
+    const int G = (K + NKB * 16 - 1) / (NKB * 16);
+    auto fn = unit ? ttm_bf16_kernel<NKB, NKS, X3, true> : ttm_bf16_kernel<NKB, NKS, X3, false>;
+    int per_cu = 1;
+    TK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kMtThreads, 0));
+    if (per_cu < 1) per_cu = 1;
+    const int64_t nblk = (ncols + 15) / 16;
+    int64_t want = ((int64_t)per_cu * device_cu_count() + G - 1) / G;
+    int64_t P = (nblk + kMtWaves - 1) / kMtWaves;
+    if (P > want) P = want;
+    if (P < 1) return TK_OK;
+    hipLaunchKernelGGL(fn, dim3((unsigned)P, G), dim3(kMtThreads), 0, st, y, v.L, ncols, v.J, m,
+                       ldm, K, transpose, z);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+// NKB * NKS <= 16 keeps the fragment table at 32 KB of LDS.
+template <int NKS, bool X3>
+static int mt_pick_kb(const float* y, const ModeView& v, const double* m, int64_t ldm, int K,
+                      int transpose, float* z, hipStream_t st) {
+    constexpr int kbmax = 16 / NKS < 4 ? 16 / NKS : 4;
+    const int need = (K + 15) / 16;
+    if (need <= 1 || kbmax == 1) return mt_launch<1, NKS, X3>(y, v, m, ldm, K, transpose, z, st);
+    if constexpr (kbmax >= 2) {
+        if (need <= 2 || kbmax == 2)
+            return mt_launch<2, NKS, X3>(y, v, m, ldm, K, transpose, z, st);
+    }
+    if constexpr (kbmax >= 4) return mt_launch<4, NKS, X3>(y, v, m, ldm, K, transpose, z, st);
+    return fail(TK_ERR_UNSUPPORTED, "bf16 ttm: no tile for K=%d", K);
+}
+
+template <bool X3>
+static int mt_dispatch(const float* y, const ModeView& v, const double* m, int64_t ldm, int K,
+                       int transpose, float* z, hipStream_t st) {
+    const int nks = (v.J + 31) / 32;
+    if (nks <= 1) return mt_pick_kb<1, X3>(y, v, m, ldm, K, transpose, z, st);
+    if (nks <= 2) return mt_pick_kb<2, X3>(y, v, m, ldm, K, transpose, z, st);
+    if (nks <= 4) return mt_pick_kb<4, X3>(y, v, m, ldm, K, transpose, z, st);
+    if (nks <= 8) return mt_pick_kb<8, X3>(y, v, m, ldm, K, transpose, z, st);
+    if (nks <= 16) return mt_pick_kb<16, X3>(y, v, m, ldm, K, transpose, z, st);
+    return fail(TK_ERR_UNSUPPORTED, "mode extent %d exceeds %d", v.J, TK_MAX_MODE_DIM);
 }
 
 int launch_ttm_mixed(const float* y, const ModeView& v, const double* m, int64_t K, int64_t ldm,
                      int transpose, int precision, float* z, hipStream_t st) {
-    (void)y; (void)v; (void)m; (void)K; (void)ldm; (void)transpose; (void)precision; (void)z;
-    (void)st;
-    return fail(TK_ERR_UNSUPPORTED, "bf16 TTM not built");
+    if (precision == TK_TTM_BF16X3) return mt_dispatch<true>(y, v, m, ldm, (int)K, transpose, z, st);
+    return mt_dispatch<false>(y, v, m, ldm, (int)K, transpose, z, st);
 }
 
 }  // namespace tk

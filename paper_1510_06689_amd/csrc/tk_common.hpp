@@ -144,7 +144,8 @@ struct Carver {
 
 struct GramPlan {
     int KT, P, G, npairs, pairs_per_group, nb;
-    size_t partial_bytes;
+    size_t partial_bytes;  // this shape's partials
+    size_t partial_bound;  // partials of any shape with this mode extent (grid cap)
 };
 GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes);
 GramPlan plan_gram_mixed(const ModeView& v);
@@ -171,9 +172,22 @@ struct EigArgs {
     double* u;             // J x R (capacity J * J)
     int64_t* rank_out;     // device
     double* disc_out;      // device
-    int* flags;            // device status flags (bit 0: no convergence, bit 1: capacity)
+    int* flags;            // device status flags (bit 0: no convergence, bit 1: capacity,
+                           // bit 2: rank within the guard margin)
     double* scratch;       // eig_scratch_doubles(J)
+    double guard = 0.0;    // > 0: flag a rank decision closer to the threshold than
+                           // guard * trace * R (J - R) / J^2 (mixed-precision Grams)
 };
+
+// Error scale of the split-bf16 Gram in the trailing eigenvalue sums, per
+// unit of trace * R (J - R) / J^2: signal/tail coupling through the bf16
+// residuals is about 2^-30 there; the guard keeps a factor 8 above it.
+constexpr double kSplitGramGuard = 8.0 / 1073741824.0;
+
+// The split-bf16 TTM leaves a relative error of about 2^-17 in every output,
+// which adds about 2^-34 ||X||^2 to later modes' tail sums; below
+// eps^2 / N = 8 * 2^-34 the threshold would feel it, so the TTMs run in FP64.
+constexpr double kSplitTtmFloor = 8.0 / 17179869184.0;
 size_t eig_scratch_doubles(int J);
 int launch_eig(const EigArgs& a, hipStream_t st);
 

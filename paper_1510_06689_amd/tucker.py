@@ -29,6 +29,7 @@ MAX_NDIM = 8
 F64, F32 = 0, 1
 GRAM_PRECISIONS = {"fp64": 0, "split_bf16": 1}
 TTM_PRECISIONS = {"fp64": 0, "bf16": 1, "bf16x3": 2}
+_TTM_NAMES = {v: k for k, v in TTM_PRECISIONS.items()}
 STATUS = {0: "TK_OK", -1: "TK_ERR_INVALID_ARG", -2: "TK_ERR_UNSUPPORTED",
           -3: "TK_ERR_WORKSPACE", -4: "TK_ERR_HIP", -5: "TK_ERR_NONFINITE",
           -6: "TK_ERR_EIG_NO_CONVERGENCE", -7: "TK_ERR_CAPACITY"}
@@ -61,7 +62,8 @@ class Tucker(ctypes.Structure):
     _fields_ = [("core_dev", ctypes.c_void_p), ("core_capacity", ctypes.c_int64),
                 ("factors_dev", ctypes.c_void_p * MAX_NDIM), ("eigvals_dev", ctypes.c_void_p),
                 ("ranks", ctypes.c_int64 * MAX_NDIM), ("discarded", ctypes.c_double * MAX_NDIM),
-                ("norm2", ctypes.c_double)]
+                ("norm2", ctypes.c_double), ("fp64_modes", ctypes.c_uint32),
+                ("ttm_precision_used", ctypes.c_int32)]
 
 
 _lib = None
@@ -223,6 +225,8 @@ class TuckerTensor:
     eigvals: list                 # per-mode Gram spectra (FP64, descending)
     discarded: tuple              # discarded eigenvalue mass per mode
     norm2: float                  # ||X||^2
+    fp64_modes: tuple = ()        # modes whose split-bf16 Gram was redone in FP64
+    ttm_precision: str = "fp64"   # arithmetic the TTMs actually ran in
 
     @property
     def full_dims(self):
@@ -310,7 +314,9 @@ class Compressor:
             off += d
         return TuckerTensor(core, factors, ranks, eig,
                             tuple(float(self.out.discarded[k]) for k in range(n)),
-                            float(self.out.norm2))
+                            float(self.out.norm2),
+                            tuple(k for k in range(n) if self.out.fp64_modes >> k & 1),
+                            _TTM_NAMES[int(self.out.ttm_precision_used)])
 
 
 def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
@@ -321,7 +327,8 @@ def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
     c.run(x)
     r = c.result()
     return TuckerTensor(_fortran_copy(r.core), [_fortran_copy(f) for f in r.factors], r.ranks,
-                        [e.clone() for e in r.eigvals], r.discarded, r.norm2)
+                        [e.clone() for e in r.eigvals], r.discarded, r.norm2, r.fp64_modes,
+                        r.ttm_precision)
 
 
 def _fortran_copy(t: torch.Tensor) -> torch.Tensor:
