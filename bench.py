@@ -90,6 +90,21 @@ def cpu_baseline(x_dev, eps, path):
                       f"single-threaded"}
 
 
+def measured_traffic(name):
+    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's readings), or None when the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes"] if sha == rec["source_sha256"] else None
+
+
 def time_ttm(x, mode, u, precision, reps, stream):
     """Average duration of one ttm_mode_n launch (Y x_n U^T) on the stream."""
     import ctypes
@@ -154,6 +169,25 @@ def kernel_rates(x, res, gp, tp, reps, stream):
             "ttm_gbs": round((b + zbytes) / tt / 1e9, 1)}
 
 
+def profile_kernels(w, dev, stream):
+    """Launches for hardware-counter runs: 3x the mode-1 split Gram, 3x the
+    mode-1 split TTM (R = 16) and 3x a plain copy of the same FP32 tensor,
+    whose byte counts calibrate the FETCH_SIZE / WRITE_SIZE counters."""
+    x = w.make(dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    res = tucker.sthosvd(x, w.eps, gram_precision="split_bf16", ttm_precision="bf16x3")
+    u = res.factors[0]
+    time_gram(x, 0, "split_bf16", 2, stream)          # 1 warm + 2 timed launches
+    time_ttm(x, 0, u, "bf16x3", 2, stream)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    nb = x.numel() * x.element_size()
+    log(f"profile-kernels: tensor {nb} bytes; copy reads {nb} and writes {nb} bytes per launch; "
+        f"ttm writes {nb // w.dims[0] * res.ranks[0]} bytes per launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +197,9 @@ def main():
                     help="both: the mixed path is the headline, the FP64 path its reference")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gram-reps", type=int, default=10)
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="counter runs: only the mode-1 split Gram and TTM of the FP32 tensor "
+                         "and a plain copy of it (3 launches each), no timing line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -174,6 +211,9 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     w = synth.WORKLOADS["combustion128"]
+    if args.profile_kernels:
+        profile_kernels(w, dev, stream)
+        return
     log(f"generating {w.name} {w.dims} on {dev}")
     x64 = w.make(dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -203,7 +243,8 @@ def main():
     if head == "mixed":
         achieved = in_bytes / (k["gram_ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("gram_split_bf16_combustion128"),
                 "kernel": "gram_partial_bf16s (mode 1, J=128, FP32 input)",
                 "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": k["gram_ms"]}
     else:
