@@ -142,7 +142,18 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds,
     return c;
 }
 
-template <bool A_IN_LDS>
+// Sum over the 8 consecutive lanes of a row group (every lane gets the same
+// bits: each step adds the same two values in either order).
+__device__ __forceinline__ double row8_sum(double v) {
+    v += dpp_move<0xb1, 0xf, false>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e, 0xf, false>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xf, false>(v);  // row_half_mirror
+    return v;
+}
+
+// JP = 32, 64, 128: A lives in registers during the tridiagonalisation
+// (J <= JP); JP = 0: A lives in the global scratch (J > 128).
+template <int JP>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region) {
     extern __shared__ double smem[];
     const int J = a.J;
@@ -160,9 +171,136 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
     double* colv = dots + J;     // J: w during step 1
     double* red = colv + J;      // 64
     int* misc = (int*)(red + 64);  // [0] = R
-    double* A = A_IN_LDS ? reg : a.scratch;   // row-major J x J
     double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
     double* X = a.u;                          // column-major J x R
+
+    if constexpr (JP > 0) {
+    // ---- 1. Householder tridiagonalisation, A in registers ---------------
+    // Thread t owns row i = t / 8 and the columns j = t % 8 + 8 q.  Per column
+    // k: the owners of row k publish it (= column k), every wave forms the
+    // reflector's scalars from it (same bits everywhere), w = A22 v is a sum
+    // over the row's 8 lanes, p = b w is published, and each thread updates
+    // its own elements.  Vectors alternate between two LDS buffers so that two
+    // barriers per column suffice; reflectors collect in LDS and go to the
+    // global scratch once at the end.
+    constexpr int NQ = JP / 8;
+    const int ri = tid >> 3, rc = tid & 7;
+    const bool rowok = ri < J;
+    double av[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = rc + 8 * q;
+        av[q] = (rowok && j < J) ? a.s[ri + (size_t)J * j] : 0.0;
+    }
+    double* Hs = reg;
+    constexpr int NS = (JP + 63) / 64;  // per-lane slots of a wave-wide reduction
+    // Straight-line code below: every load stays inside four JP-long vector
+    // buffers (zeroed first, so stale entries are finite; they sit in the
+    // 1024-double area after misc, which only the global-A path uses), and
+    // inactive terms are removed by exact 0/1 factors rather than by branches.
+    static_assert(4 * JP <= kEigThreads, "vector buffers must fit the partial-sum area");
+    double* vbuf = red + 64 + 8;
+    for (int i = tid; i < 4 * JP; i += kEigThreads) vbuf[i] = 0.0;
+    __syncthreads();
+    for (int k = 0; k + 2 < J; ++k) {
+        double* xs = vbuf + (k & 1) * JP;
+        double* ps = vbuf + (2 + (k & 1)) * JP;
+        double* sg = red + 40 + (k & 1);  // sigma of column k
+        if (ri == k) {
+            // the owners publish column k and sigma = sum_{j > k+1} x_j^2
+            double sq = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = rc + 8 * q;
+                xs[j] = av[q];
+                sq = fma(((j >= k + 2 && j < J) ? 1.0 : 0.0) * av[q], av[q], sq);
+            }
+            sq = row8_sum(sq);
+            if (rc == 0) *sg = sq;
+            if ((k & 7) == rc) d[k] = av[k >> 3];
+        }
+        __syncthreads();
+        const double sigma = *sg;
+        const double x0 = xs[k + 1];
+        double b, mu, v0;
+        if (sigma == 0.0) {
+            b = 0.0;
+            mu = x0;
+            v0 = 1.0;
+        } else {
+            mu = sqrt(x0 * x0 + sigma);
+            v0 = (x0 <= 0.0) ? x0 - mu : -sigma * recip(x0 + mu);
+            b = 2.0 * v0 * v0 * recip(sigma + v0 * v0);
+        }
+        if (tid == 0) {
+            e[k] = mu;
+            beta[k] = b;
+        }
+        if (b == 0.0) continue;  // uniform: the reflector is the identity
+        const double inv_v0 = recip(v0);
+        double vq[NQ];
+        double pr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = rc + 8 * q;
+            const double xj = xs[j];
+            vq[q] = ((j > k && j < J) ? 1.0 : 0.0) * (j == k + 1 ? 1.0 : xj * inv_v0);
+            pr[q & 3] = fma(av[q], vq[q], pr[q & 3]);
+        }
+        double part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
+        if (rc == 0 && ri > k && rowok) ps[ri] = b * part;
+        if (ri == k) {  // reflector k: Hs[k J + j] = v_j (entries j <= k are never read)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) Hs[(size_t)k * J + rc + 8 * q] = vq[q];
+        }
+        __syncthreads();
+        // A22 -= v p^T + p v^T - 2 kc v v^T with 2 kc = b p.v (every wave the
+        // same bits), in a commutative form so that A stays exactly symmetric
+        double pv = 0.0;
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+            const int j = lane + 64 * r;
+            const int jc = j < JP ? j : 0;
+            const double mj = (j >= k + 1 && j < J) ? 1.0 : 0.0;
+            const double vj = j == k + 1 ? 1.0 : xs[jc] * inv_v0;
+            pv = fma(mj * ps[jc], vj, pv);
+        }
+        const double kc2 = b * wave_sum(pv);
+        const double mrow = (ri > k && rowok) ? 1.0 : 0.0;
+        const int ric = ri < JP ? ri : 0;
+        const double vi = ri == k + 1 ? 1.0 : xs[ric] * inv_v0;
+        const double pi = ps[ric];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = rc + 8 * q;
+            const double vj = vq[q], pj = ps[j];
+            const double t = __dadd_rn(__dmul_rn(vi, pj), __dmul_rn(pi, vj));
+            const double du = __dsub_rn(t, __dmul_rn(kc2, __dmul_rn(vi, vj)));
+            av[q] -= (mrow * ((j > k && j < J) ? 1.0 : 0.0)) * du;
+        }
+    }
+    // the trailing 2 x 2 block (or 1 x 1)
+    if (ri >= J - 2 && rowok) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = rc + 8 * q;
+            if (j == ri) d[ri] = av[q];
+            if (ri == J - 2 && j == J - 1) e[J - 2] = av[q];
+        }
+    }
+    if (tid == 0) {
+        if (J >= 2) beta[J - 2] = 0.0;
+        e[J - 1] = 0.0;
+        beta[J - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) {
+        const int k = idx / J, i = idx - k * J;
+        if (i < J - k - 1) H[idx] = Hs[idx + k + 1];
+    }
+    __syncthreads();
+    } else {
+    double* A = a.scratch;  // row-major J x J
 
     // ---- load S (symmetric) -------------------------------------------
     for (int idx = tid; idx < J * J; idx += kEigThreads) A[idx] = a.s[idx];
@@ -265,6 +403,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
         if (i < J - k - 1) H[idx] = A[(size_t)(k + 1 + i) * J + k];
     }
     __syncthreads();
+    }
     if (tid == 0) {
         double gl = DBL_MAX, gu = -DBL_MAX;
         for (int i = 0; i < J; ++i) {
@@ -370,6 +509,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
     }
     __syncthreads();
     const int R = misc[0];
+
 
     // ---- 4. inverse iteration, batches of vectors held in LDS -----------
     const double tiny = DBL_EPSILON * tnorm + DBL_MIN;
@@ -582,12 +722,12 @@ int launch_eig(const EigArgs& a, hipStream_t st) {
     const int region = (int)eig_region_doubles(a.J);
     const size_t lds = ((size_t)region + eig_small_doubles(a.J)) * sizeof(double);
     if (a.J <= 128) {
-        auto fn = eig_kernel<true>;
+        auto fn = a.J <= 32 ? eig_kernel<32> : a.J <= 64 ? eig_kernel<64> : eig_kernel<128>;
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
         hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
     } else {
-        auto fn = eig_kernel<false>;
+        auto fn = eig_kernel<0>;
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
         hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);

@@ -1,0 +1,131 @@
+"""Parity at the benchmark's full size (combustion128: 128x128x128x32x32,
+17.2 GB in FP64, 8.6 GB in FP32), in the configuration bench.py times.
+
+The oracle cannot process the whole tensor in a test's time, so it checks
+what it can compute one by one -- Gram entries of mode 1 from two-row slices
+of the unfolding, TTM output columns from single input columns -- and the
+run is checked against properties that hold at any size: the planted ranks,
+the identity ||X||^2 - ||G||^2 = sum of discarded eigenvalues = ||X - X~||^2
+(ST-HOSVD, from orthogonality of the factors), orthonormal factors, and for
+the mixed path ranks equal to the FP64 path's with relative errors within
+1e-4 of each other."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1510_06689_amd import tucker
+from gpu_util import U32, U64, say
+
+pytestmark = pytest.mark.gpu
+
+W = synth.WORKLOADS["combustion128"]
+PAIRS = [(0, 0), (3, 77), (64, 1), (127, 127), (90, 91)]
+COLS = [0, 1, 12345, 2**23 + 7, 2**24 - 1]   # mode-1 columns (other-mode multi-index)
+
+
+@pytest.fixture(scope="module")
+def tensors():
+    say(f"generating {W.name} {W.dims}")
+    x64 = W.make(dtype=torch.float64, device="cuda:0")
+    x32 = tucker.empty_fortran(W.dims, torch.float32, "cuda:0")
+    x32.copy_(x64)
+    torch.cuda.synchronize()
+    yield x64, x32
+    del x64, x32
+    torch.cuda.empty_cache()
+
+
+def _rows(x, i, j):
+    """Rows i and j of the mode-1 unfolding as a 2 x I2 x .. x I5 host tensor."""
+    out = np.empty((2,) + tuple(x.shape[1:]), order="F")
+    out[0] = x[i].double().cpu().numpy()
+    out[1] = x[j].double().cpu().numpy()
+    return out
+
+
+def _split_bound(sub):
+    """Elementwise bound of the split-bf16 Gram for a two-row slice."""
+    m = oracle.unfold(sub, 0)
+    rmax = np.abs(m).max(axis=1)
+    l1 = np.abs(m).sum(axis=1)
+    k = m.shape[1]
+    return 2.0**-16 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-24 * k * np.outer(rmax, rmax)
+
+
+@pytest.mark.parametrize("path", ["fp64", "mixed"])
+def test_fullsize_mode1_gram_entries(tensors, path):
+    x = tensors[0] if path == "fp64" else tensors[1]
+    prec = "fp64" if path == "fp64" else "split_bf16"
+    s, sumsq = tucker.gram(x, 0, precision=prec)
+    torch.cuda.synchronize()
+    s = s.cpu().numpy()
+    k = x.numel() // x.shape[0]
+    for i, j in PAIRS:
+        sub = _rows(x, i, j)
+        ref = oracle.gram(sub, 0)                       # [[S_ii, S_ij], [S_ji, S_jj]]
+        d = np.sqrt(np.diag(ref))
+        tol = (k + 2) * U64 * np.outer(d, d)
+        if path == "mixed":
+            tol = tol + _split_bound(sub)
+        got = np.array([[s[i, i], s[i, j]], [s[j, i], s[j, j]]])
+        say(f"{path} S[{i},{j}] = {got[0, 1]:.12e} oracle {ref[0, 1]:.12e}")
+        assert np.all(np.abs(got - ref) <= tol), (i, j, got - ref, tol)
+
+
+@pytest.mark.parametrize("path", ["fp64", "mixed"])
+def test_fullsize_mode1_ttm_columns(tensors, path):
+    x = tensors[0] if path == "fp64" else tensors[1]
+    prec = "fp64" if path == "fp64" else "bf16x3"
+    rng = np.random.default_rng(7)
+    u = np.linalg.qr(rng.standard_normal((x.shape[0], 16)))[0]        # orthonormal, J x R
+    ud = tucker.empty_colmajor(u.shape[0], u.shape[1], "cuda:0").copy_(torch.as_tensor(u))
+    z = tucker.ttm(x, 0, ud, transpose=True, precision=prec)          # 16 x 128 x .. x 32
+    torch.cuda.synchronize()
+    xf = x.permute(*reversed(range(x.dim()))).reshape(-1, x.shape[0])   # column c -> row c
+    zf = z.permute(*reversed(range(z.dim()))).reshape(-1, z.shape[0])
+    ycols = xf[COLS].double().cpu().numpy().T                          # 128 x ncols
+    zcols = zf[COLS].double().cpu().numpy().T
+    ref = oracle.ttm(np.asfortranarray(ycols), 0, u.T)                   # Z_(1) = U^T Y_(1)
+    absprod = oracle.ttm(np.asfortranarray(np.abs(ycols)), 0, np.abs(u.T))
+    if path == "fp64":
+        tol = 130 * U64 * absprod
+    else:
+        tol = (4 * 2.0**-16 + 16 * 2.0**-24) * absprod + U32 * np.abs(ref)
+    assert np.all(np.abs(zcols - ref) <= tol + 1e-300), np.max(np.abs(zcols - ref) / (tol + 1e-300))
+
+
+def _check_invariants(x, res, eps, tol_rel, tol_norm):
+    nu = res.norm2
+    g2 = float((res.core.double() ** 2).sum().item())
+    disc = float(sum(res.discarded))
+    xh = tucker.reconstruct(res.core, res.factors)
+    e2, _, n2 = tucker.error_metrics(x, xh)
+    del xh
+    torch.cuda.empty_cache()
+    assert math.isclose(n2, nu, rel_tol=tol_norm)   # ||X||^2: error metric vs first Gram's trace
+    assert abs((nu - g2) - disc) <= tol_rel * nu, (nu - g2, disc)
+    assert abs(e2 - disc) <= tol_rel * nu, (e2, disc)
+    assert math.sqrt(e2 / nu) <= eps
+    for u in res.factors:
+        ut = u.cpu().numpy()
+        assert np.abs(ut.T @ ut - np.eye(ut.shape[1])).max() <= 1e-12
+    return math.sqrt(e2 / nu)
+
+
+def test_fullsize_sthosvd_fp64_and_mixed(tensors):
+    x64, x32 = tensors
+    r64 = tucker.sthosvd(x64, W.eps)
+    assert r64.ranks == W.ranks
+    rel64 = _check_invariants(x64, r64, W.eps, 64 * U64 * 100, 1e-12)
+    rm = tucker.sthosvd(x32, W.eps, gram_precision="split_bf16", ttm_precision="bf16x3")
+    say(f"ranks fp64 {r64.ranks} mixed {rm.ranks} fp64-redone modes {rm.fp64_modes}")
+    assert rm.ranks == r64.ranks
+    # FP32 storage and split products: the identity holds to the TTMs' ~2^-17,
+    # and the first Gram's trace carries the split's ~2^-16 / sqrt(K) relative error
+    relm = _check_invariants(x32, rm, W.eps, 1e-6, 1e-6)
+    say(f"relerr fp64 {rel64:.6e} mixed {relm:.6e}")
+    assert abs(relm - rel64) <= 1e-4
