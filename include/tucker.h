@@ -222,6 +222,63 @@ size_t error_metrics_workspace_bytes(const tk_shape* x);
 
 /* --------------------------------------------------------------- helpers */
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (each an ST-HOSVD as in sthosvd_compress; the
+ * problems may have different extents) compressed together: every mode step
+ * of every problem runs in a handful of launches that cover the whole batch
+ * (a split-bf16 Gram, its reduction, one eigensolver workgroup per problem,
+ * a split-bf16 TTM), with each problem's later shapes derived on the device
+ * from the ranks found there.  sthosvd_batch_run therefore enqueues work
+ * without any host synchronisation, allocation or memset: it can be captured
+ * into a HIP graph once and replayed.
+ *
+ * Requirements: TK_F32 storage, gram_precision TK_GRAM_SPLIT_BF16,
+ * ttm_precision TK_TTM_BF16X3 or TK_TTM_BF16 (TK_TTM_BF16X3 needs
+ * eps^2/N >= 2^-31 under the eps rule), every problem with the same ndim and
+ * mode order, every extent <= 128.
+ *
+ * A problem whose rank the split Gram could not certify (status bit 4, see
+ * TK_GRAM_SPLIT_BF16) is recomputed, with the FP64 fallback of
+ * sthosvd_compress, by sthosvd_batch_finish. */
+typedef struct tk_batch tk_batch; /* opaque host-side plan */
+
+typedef struct tk_batch_outputs {
+    void* const* core_dev;          /* [batch] core buffers (FP32, natural layout) */
+    const int64_t* core_capacity;   /* [batch] elements available at core_dev[b] */
+    double* const* factors_dev;     /* [batch * TK_MAX_NDIM] U_n, capacity I_n * I_n each */
+    int64_t* ranks_dev;             /* device [batch * ndim] */
+    double* discarded_dev;          /* device [batch * ndim] */
+    double* norm2_dev;              /* device [batch] */
+    int32_t* status_dev;            /* device [batch * 2]: [0] bit 1 = capacity exceeded,
+                                       bit 2 = rank not certified (redone by finish);
+                                       [1] bit n = mode n redone in FP64 by finish */
+} tk_batch_outputs;
+
+/* Work partition: column tiles per Gram workgroup and 16-column blocks per
+ * TTM workgroup, per mode (0 = default).  Chosen by an autotuner in the
+ * Python layer; any positive values give the same results up to summation
+ * order. */
+typedef struct tk_batch_tuning {
+    int32_t gram_tiles_per_wg[TK_MAX_NDIM];
+    int32_t ttm_blocks_per_wg[TK_MAX_NDIM];
+} tk_batch_tuning;
+
+size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt);
+/* Validates, lays out the workspace (device, caller-owned, 256-byte aligned)
+ * and uploads the task tables (one synchronous copy).  x_dev[b] and every
+ * output pointer are bound into the plan.  *handle receives a host object
+ * freed by sthosvd_batch_destroy. */
+int sthosvd_batch_create(int batch, const tk_shape* shapes, const void* const* x_dev,
+                         const tk_options* opt, const tk_batch_tuning* tuning,
+                         const tk_batch_outputs* out, void* ws, size_t ws_bytes, void* stream,
+                         tk_batch** handle);
+/* Enqueues one compression of every problem (no sync, allocation or memset). */
+int sthosvd_batch_run(tk_batch* handle, void* stream);
+/* Synchronises, redoes the problems with status bit 4 set, reports
+ * capacity errors (TK_ERR_CAPACITY). */
+int sthosvd_batch_finish(tk_batch* handle, void* stream);
+void sthosvd_batch_destroy(tk_batch* handle);
+
 const char* tk_status_string(int status);
 const char* tk_last_error(void);
 

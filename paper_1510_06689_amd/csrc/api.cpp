@@ -46,7 +46,7 @@ int check_shape(const tk_shape* s, const char* what) {
     return TK_OK;
 }
 
-static int check_ws(void* ws, size_t ws_bytes, size_t need, const char* what) {
+int check_ws(void* ws, size_t ws_bytes, size_t need, const char* what) {
     if (ws_bytes < need)
         return fail(TK_ERR_WORKSPACE, "%s: workspace %zu bytes < required %zu", what, ws_bytes,
                     need);

@@ -1,0 +1,429 @@
+// Batches of independent ST-HOSVD problems (Alg. 1 per problem): host-side
+// planning, the enqueue-only run (graph-capturable) and the finishing step.
+//
+// Every mode step s of the common mode order runs, for the whole batch, as
+//   split-bf16 Gram  (one launch per padded-extent class, workgroups dealt
+//                     to problems in proportion to their capacity-size tiles)
+//   reduction        (one launch; step 0 also forms ||X||^2 per problem)
+//   eigensolver      (one workgroup per problem, rank rule and guard on the
+//                     device)
+//   split-bf16 TTM   (one launch per extent class; each problem's rank read
+//                     from device memory)
+// with each problem's shapes at later steps derived on the device from its
+// ranks.  Buffers are laid out at the rank capacities, so the plan -- the
+// device task tables -- is fixed and uploaded once.
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+#include <array>
+#include <map>
+#include <vector>
+
+#include "tk_common.hpp"
+
+using namespace tk;
+
+namespace {
+
+struct GramLaunch {
+    int jb, ntasks, total_wg;
+    size_t off;  // byte offset of its tasks in the table area
+};
+struct TtmLaunch {
+    int J, kmax, ntasks, total_wg;
+    size_t off;
+};
+struct StepPlan {
+    std::vector<GramLaunch> grams;
+    size_t red_off = 0;
+    int red_ntasks = 0, red_wg = 0;
+    size_t eig_off = 0;
+    int jmax = 0;
+    std::vector<TtmLaunch> ttms;
+};
+
+constexpr int kDefaultGramTilesPerWg = 16;
+constexpr int kDefaultTtmBlocksPerWg = 64;
+
+int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+int round_pow2_32(int J) {
+    int jb = 32;
+    while (jb < J) jb *= 2;
+    return jb;
+}
+
+}  // namespace
+
+struct tk_batch {
+    int B = 0, N = 0;
+    int order[TK_MAX_NDIM];
+    std::vector<tk_shape> shapes;
+    std::vector<const void*> x;
+    tk_options opt{};
+    std::vector<int32_t> mode_order;
+    std::vector<int64_t> fixed, maxr;
+    std::vector<void*> cores;
+    std::vector<int64_t> core_cap;
+    std::vector<double*> factors;  // B * TK_MAX_NDIM
+    int64_t* ranks_dev = nullptr;
+    double* disc_dev = nullptr;
+    double* norm2_dev = nullptr;
+    int32_t* status_dev = nullptr;
+    std::vector<StepPlan> steps;
+    char* tables_dev = nullptr;
+    std::vector<double*> lam;  // per problem, sum of extents
+    void* single_ws = nullptr;
+    size_t single_ws_bytes = 0;
+};
+
+namespace {
+
+// Validation shared by the size query and create.
+int check_batch(int batch, const tk_shape* shapes, const tk_options* opt) {
+    if (batch < 1) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: batch %d < 1", batch);
+    if (!shapes || !opt) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: NULL shapes or options");
+    const int N = shapes[0].ndim;
+    for (int b = 0; b < batch; ++b) {
+        TK_TRY(check_shape(&shapes[b], "sthosvd_batch"));
+        if (shapes[b].ndim != N)
+            return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: problem %d has ndim %d != %d", b,
+                        shapes[b].ndim, N);
+        if (shapes[b].dtype != TK_F32)
+            return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: problems must be stored FP32");
+        for (int k = 0; k < N; ++k)
+            if (shapes[b].dims[k] > 128)
+                return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: extent %lld > 128",
+                            (long long)shapes[b].dims[k]);
+    }
+    if (!(opt->eps >= 0.0) || !std::isfinite(opt->eps))
+        return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: eps must be finite and >= 0");
+    if (opt->gram_precision != TK_GRAM_SPLIT_BF16)
+        return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: needs gram_precision TK_GRAM_SPLIT_BF16");
+    if (opt->ttm_precision != TK_TTM_BF16X3 && opt->ttm_precision != TK_TTM_BF16)
+        return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: needs a bf16 TTM precision");
+    if (opt->ttm_precision == TK_TTM_BF16X3 && !opt->fixed_ranks &&
+        opt->eps * opt->eps / N < kSplitTtmFloor)
+        return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: eps below the split TTM's accuracy");
+    bool seen[TK_MAX_NDIM] = {false};
+    for (int k = 0; k < N; ++k) {
+        const int n = opt->mode_order ? opt->mode_order[k] : k;
+        if (n < 0 || n >= N || seen[n])
+            return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: mode_order is not a permutation");
+        seen[n] = true;
+    }
+    for (int b = 0; b < batch; ++b)
+        for (int n = 0; n < N; ++n) {
+            if (opt->fixed_ranks && (opt->fixed_ranks[n] < 1 || opt->fixed_ranks[n] > shapes[b].dims[n]))
+                return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: fixed_ranks[%d] out of range", n);
+            if (opt->max_ranks && opt->max_ranks[n] < 1)
+                return fail(TK_ERR_INVALID_ARG, "sthosvd_batch: max_ranks[%d] < 1", n);
+        }
+    return TK_OK;
+}
+
+int64_t cap_of(const tk_shape& sh, const tk_options* opt, int n) {
+    int64_t c = sh.dims[n];
+    if (opt->max_ranks && opt->max_ranks[n] < c) c = opt->max_ranks[n];
+    if (opt->fixed_ranks && opt->fixed_ranks[n] < c) c = opt->fixed_ranks[n];
+    return c;
+}
+
+// Lays out the workspace and, when h is non-null, fills the host-side plan
+// and the task tables (returned in `tables`, copied to the device by create).
+// Returns the workspace bytes.
+size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk_batch_tuning* tn,
+                  void* ws, tk_batch* h, std::vector<char>* tables) {
+    const int N = shapes[0].ndim;
+    int order[TK_MAX_NDIM];
+    for (int k = 0; k < N; ++k) order[k] = opt->mode_order ? opt->mode_order[k] : k;
+    Carver c(ws, ~size_t(0) >> 1);
+    // per-problem buffers
+    struct Bufs {
+        void* y[2];
+        double *partial, *S, *scratch, *lam;
+    };
+    std::vector<Bufs> bufs(B);
+    size_t single = 0;
+    for (int b = 0; b < B; ++b) {
+        const tk_shape& sh = shapes[b];
+        int64_t capcur[TK_MAX_NDIM];
+        for (int k = 0; k < N; ++k) capcur[k] = sh.dims[k];
+        size_t yb[2] = {0, 0}, pb = 0;
+        int jmax = 1;
+        for (int s = 0; s < N; ++s) {
+            const int n = order[s];
+            const ModeView v = mode_view(capcur, N, n);
+            const int jb = round_pow2_32(v.J);
+            const int nb16 = 2 * (jb / 32), np16 = nb16 * (nb16 + 1) / 2;
+            const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
+                                                               : kDefaultGramTilesPerWg;
+            const int nwg = std::max(1, std::min(4096, ceil_div(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw)));
+            pb = std::max(pb, (size_t)nwg * np16 * 256 * sizeof(double));
+            jmax = std::max(jmax, v.J);
+            capcur[n] = cap_of(sh, opt, n);
+            if (s + 1 < N) {
+                int64_t ne = 1;
+                for (int k = 0; k < N; ++k) ne *= capcur[k];
+                yb[s & 1] = std::max(yb[s & 1], (size_t)ne * sizeof(float));
+            }
+        }
+        int64_t sumd = 0;
+        for (int k = 0; k < N; ++k) sumd += sh.dims[k];
+        bufs[b].y[0] = c.take(yb[0]);
+        bufs[b].y[1] = c.take(yb[1]);
+        bufs[b].partial = (double*)c.take(pb);
+        bufs[b].S = (double*)c.take((size_t)jmax * jmax * sizeof(double));
+        bufs[b].scratch = (double*)c.take(eig_scratch_doubles(jmax) * sizeof(double));
+        bufs[b].lam = (double*)c.take((size_t)sumd * sizeof(double));
+        tk_options o1 = *opt;  // the finishing step's single-problem runs
+        single = std::max(single, sthosvd_workspace_bytes(&sh, &o1));
+    }
+    void* single_ws = c.take(single);
+
+    // task tables: build on the host in one byte array
+    std::vector<char> tab;
+    auto put = [&](const void* p, size_t n) {
+        size_t o = (tab.size() + 15) & ~size_t(15);
+        tab.resize(o + n);
+        memcpy(tab.data() + o, p, n);
+        return o;
+    };
+    std::vector<StepPlan> steps(N);
+    int done = 0;
+    std::vector<std::array<int64_t, TK_MAX_NDIM>> capcur(B);
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < N; ++k) capcur[b][k] = shapes[b].dims[k];
+    for (int s = 0; s < N; ++s) {
+        const int n = order[s];
+        StepPlan& sp = steps[s];
+        // Gram tasks, grouped by padded-extent class
+        std::map<int, std::vector<BatchGramTask>> gclass;
+        std::map<int, std::vector<BatchTtmTask>> tclass;
+        std::map<int, int> tkmax;
+        std::vector<BatchReduceTask> red;
+        std::vector<EigArgs> eig(B);
+        int red_wg = 0;
+        for (int b = 0; b < B; ++b) {
+            const tk_shape& sh = shapes[b];
+            const ModeView v = mode_view(capcur[b].data(), N, n);
+            const int jb = round_pow2_32(v.J);
+            const int nb16 = 2 * (jb / 32), np16 = nb16 * (nb16 + 1) / 2;
+            const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
+                                                               : kDefaultGramTilesPerWg;
+            const int nwg = std::max(1, std::min(4096, ceil_div(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw)));
+            BatchView bv{};
+            for (int k = 0; k < N; ++k) bv.dims[k] = sh.dims[k];
+            bv.ranks = h ? h->ranks_dev + (size_t)b * N : nullptr;
+            bv.ndim = N;
+            bv.n = n;
+            bv.done = done;
+            const void* yin = s == 0 ? (h ? h->x[b] : nullptr) : bufs[b].y[(s - 1) & 1];
+            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial};
+            gt.v.nwg = nwg;
+            gclass[jb].push_back(gt);
+            BatchReduceTask rt{bufs[b].partial, bufs[b].S,
+                               s == 0 && h ? h->norm2_dev + b : nullptr, nwg, np16, nb16, v.J, 0, 0};
+            rt.nwg = ceil_div((int64_t)np16 * 256, 64) + (s == 0 ? 1 : 0);
+            rt.wg_begin = red_wg;
+            red_wg += rt.nwg;
+            red.push_back(rt);
+            int64_t lam_off = 0;
+            for (int k = 0; k < n; ++k) lam_off += sh.dims[k];
+            EigArgs& ea = eig[b];
+            ea.s = bufs[b].S;
+            ea.J = v.J;
+            ea.nu = h ? h->norm2_dev + b : nullptr;
+            ea.eps2_over_n = opt->eps * opt->eps / (double)N;
+            ea.fixed_rank = opt->fixed_ranks ? (int)opt->fixed_ranks[n] : 0;
+            ea.max_rank = (int)cap_of(sh, opt, n);
+            ea.lambda = bufs[b].lam + lam_off;
+            ea.u = h ? h->factors[(size_t)b * TK_MAX_NDIM + n] : nullptr;
+            ea.rank_out = h ? h->ranks_dev + (size_t)b * N + n : nullptr;
+            ea.disc_out = h ? h->disc_dev + (size_t)b * N + n : nullptr;
+            ea.flags = h ? h->status_dev + 2 * b : nullptr;
+            ea.scratch = bufs[b].scratch;
+            ea.guard = opt->fixed_ranks ? 0.0 : kSplitGramGuard;
+            sp.jmax = std::max(sp.jmax, v.J);
+            // TTM into the other buffer (the core at the last step)
+            void* yout = s + 1 == N ? (h ? h->cores[b] : nullptr) : bufs[b].y[s & 1];
+            const int bpw = tn && tn->ttm_blocks_per_wg[s] > 0 ? tn->ttm_blocks_per_wg[s]
+                                                               : kDefaultTtmBlocksPerWg;
+            BatchTtmTask tt{bv, (const float*)yin, ea.u, (float*)yout};
+            tt.v.nwg = std::max(1, std::min(4096, ceil_div(ceil_div(v.L * v.B, 16), bpw)));
+            const int jcls = v.J <= 32 ? 32 : v.J <= 64 ? 64 : 128;
+            tclass[jcls].push_back(tt);
+            tkmax[jcls] = std::max(tkmax[jcls], ea.max_rank);
+            capcur[b][n] = cap_of(sh, opt, n);
+        }
+        for (auto& kv : gclass) {
+            int wg = 0;
+            for (auto& t : kv.second) {
+                t.v.wg_begin = wg;
+                wg += t.v.nwg;
+            }
+            sp.grams.push_back({kv.first, (int)kv.second.size(), wg,
+                                put(kv.second.data(), kv.second.size() * sizeof(BatchGramTask))});
+        }
+        sp.red_off = put(red.data(), red.size() * sizeof(BatchReduceTask));
+        sp.red_ntasks = (int)red.size();
+        sp.red_wg = red_wg;
+        sp.eig_off = put(eig.data(), eig.size() * sizeof(EigArgs));
+        for (auto& kv : tclass) {
+            int wg = 0;
+            for (auto& t : kv.second) {
+                t.v.wg_begin = wg;
+                wg += t.v.nwg;
+            }
+            sp.ttms.push_back({kv.first, tkmax[kv.first], (int)kv.second.size(), wg,
+                               put(kv.second.data(), kv.second.size() * sizeof(BatchTtmTask))});
+        }
+        done |= 1 << n;
+    }
+    char* tables_dev = (char*)c.take(tab.size());
+    if (h) {
+        h->steps = steps;
+        h->tables_dev = tables_dev;
+        h->single_ws = single_ws;
+        h->single_ws_bytes = single;
+        h->lam.resize(B);
+        for (int b = 0; b < B; ++b) h->lam[b] = bufs[b].lam;
+        *tables = tab;
+    }
+    return c.used + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt) {
+    if (check_batch(batch, shapes, opt) != TK_OK) return 0;
+    return plan_batch(batch, shapes, opt, nullptr, nullptr, nullptr, nullptr);
+}
+
+int sthosvd_batch_create(int batch, const tk_shape* shapes, const void* const* x_dev,
+                         const tk_options* opt, const tk_batch_tuning* tuning,
+                         const tk_batch_outputs* out, void* ws, size_t ws_bytes, void* stream,
+                         tk_batch** handle) {
+    if (!handle) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_create: handle NULL");
+    *handle = nullptr;
+    TK_TRY(check_batch(batch, shapes, opt));
+    if (!x_dev || !out || !out->core_dev || !out->core_capacity || !out->factors_dev ||
+        !out->ranks_dev || !out->discarded_dev || !out->norm2_dev || !out->status_dev)
+        return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_create: NULL input or output pointer");
+    const int N = shapes[0].ndim;
+    for (int b = 0; b < batch; ++b) {
+        if (!x_dev[b] || !out->core_dev[b])
+            return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_create: problem %d has a NULL buffer", b);
+        int64_t ncore = 1;
+        for (int n = 0; n < N; ++n) {
+            if (!out->factors_dev[(size_t)b * TK_MAX_NDIM + n])
+                return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_create: factor %d of problem %d NULL",
+                            n, b);
+            ncore *= cap_of(shapes[b], opt, n);
+        }
+        if (out->core_capacity[b] < ncore)
+            return fail(TK_ERR_CAPACITY, "sthosvd_batch_create: core capacity of problem %d < %lld",
+                        b, (long long)ncore);
+    }
+    const size_t need = plan_batch(batch, shapes, opt, tuning, nullptr, nullptr, nullptr);
+    TK_TRY(check_ws(ws, ws_bytes, need, "sthosvd_batch_create"));
+
+    tk_batch* h = new tk_batch();
+    h->B = batch;
+    h->N = N;
+    h->shapes.assign(shapes, shapes + batch);
+    h->x.assign(x_dev, x_dev + batch);
+    h->opt = *opt;
+    for (int k = 0; k < N; ++k) h->order[k] = opt->mode_order ? opt->mode_order[k] : k;
+    if (opt->mode_order) {
+        h->mode_order.assign(opt->mode_order, opt->mode_order + N);
+        h->opt.mode_order = h->mode_order.data();
+    }
+    if (opt->fixed_ranks) {
+        h->fixed.assign(opt->fixed_ranks, opt->fixed_ranks + N);
+        h->opt.fixed_ranks = h->fixed.data();
+    }
+    if (opt->max_ranks) {
+        h->maxr.assign(opt->max_ranks, opt->max_ranks + N);
+        h->opt.max_ranks = h->maxr.data();
+    }
+    h->cores.assign(out->core_dev, out->core_dev + batch);
+    h->core_cap.assign(out->core_capacity, out->core_capacity + batch);
+    h->factors.assign(out->factors_dev, out->factors_dev + (size_t)batch * TK_MAX_NDIM);
+    h->ranks_dev = out->ranks_dev;
+    h->disc_dev = out->discarded_dev;
+    h->norm2_dev = out->norm2_dev;
+    h->status_dev = out->status_dev;
+    std::vector<char> tables;
+    plan_batch(batch, shapes, &h->opt, tuning, ws, h, &tables);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h->tables_dev, tables.data(), tables.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(TK_ERR_HIP, "sthosvd_batch_create: table upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    *handle = h;
+    return TK_OK;
+}
+
+int sthosvd_batch_run(tk_batch* h, void* stream) {
+    if (!h) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_run: handle NULL");
+    hipStream_t st = (hipStream_t)stream;
+    TK_TRY(launch_fill_i32((int*)h->status_dev, 2 * h->B, 0, st));
+    for (int s = 0; s < h->N; ++s) {
+        const StepPlan& sp = h->steps[s];
+        for (const GramLaunch& g : sp.grams)
+            TK_TRY(launch_gram_bf16s_batched((const BatchGramTask*)(h->tables_dev + g.off),
+                                             g.ntasks, g.total_wg, g.jb, st));
+        TK_TRY(launch_gram_reduce_batched((const BatchReduceTask*)(h->tables_dev + sp.red_off),
+                                          sp.red_ntasks, sp.red_wg, st));
+        TK_TRY(launch_eig_batched((const EigArgs*)(h->tables_dev + sp.eig_off), h->B, sp.jmax,
+                                  0, 0, st));
+        for (const TtmLaunch& t : sp.ttms)
+            TK_TRY(launch_ttm_bf16_batched((const BatchTtmTask*)(h->tables_dev + t.off),
+                                           t.ntasks, t.total_wg, t.J, t.kmax,
+                                           h->opt.ttm_precision, st));
+    }
+    return TK_OK;
+}
+
+int sthosvd_batch_finish(tk_batch* h, void* stream) {
+    if (!h) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_finish: handle NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int B = h->B, N = h->N;
+    std::vector<int32_t> status(2 * (size_t)B);
+    TK_HIP(hipMemcpyAsync(status.data(), h->status_dev, status.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
+    TK_HIP(hipStreamSynchronize(st));
+    int rc = TK_OK;
+    for (int b = 0; b < B; ++b) {
+        if (status[2 * b] & 2) rc = fail(TK_ERR_CAPACITY, "sthosvd_batch: problem %d exceeds max_ranks", b);
+        if (!(status[2 * b] & 4)) continue;
+        // the split Gram could not certify a rank of this problem: redo it
+        tk_tucker t{};
+        t.core_dev = h->cores[b];
+        t.core_capacity = h->core_cap[b];
+        for (int n = 0; n < N; ++n) t.factors_dev[n] = h->factors[(size_t)b * TK_MAX_NDIM + n];
+        t.eigvals_dev = h->lam[b];
+        TK_TRY(sthosvd_compress(&h->shapes[b], h->x[b], &h->opt, &t, h->single_ws,
+                                h->single_ws_bytes, stream));
+        int32_t st2[2] = {0, (int32_t)t.fp64_modes};
+        TK_HIP(hipMemcpyAsync(h->ranks_dev + (size_t)b * N, t.ranks, N * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st));
+        TK_HIP(hipMemcpyAsync(h->disc_dev + (size_t)b * N, t.discarded, N * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        TK_HIP(hipMemcpyAsync(h->norm2_dev + b, &t.norm2, sizeof(double), hipMemcpyHostToDevice, st));
+        TK_HIP(hipMemcpyAsync(h->status_dev + 2 * b, st2, sizeof st2, hipMemcpyHostToDevice, st));
+        TK_HIP(hipStreamSynchronize(st));
+    }
+    return rc;
+}
+
+void sthosvd_batch_destroy(tk_batch* h) { delete h; }
+
+}  // extern "C"

@@ -154,7 +154,7 @@ __device__ __forceinline__ double row8_sum(double v) {
 // JP = 32, 64, 128: A lives in registers during the tridiagonalisation
 // (J <= JP); JP = 0: A lives in the global scratch (J > 128).
 template <int JP>
-__global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region) {
+__device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     extern __shared__ double smem[];
     const int J = a.J;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -716,6 +716,50 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
             if (q < nslot && t < J) X[(size_t)j * J + t] = sgn * xr[q];
         }
     }
+}
+
+template <int JP>
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region) {
+    eig_body<JP>(a, region);
+}
+
+// One workgroup per problem of a batch.  conditional != 0: only problems whose
+// status word has the guard bit (4) run; afterwards the bit is cleared and
+// `mode_bit` is recorded in the problem's second status word.
+template <int JP>
+__global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __restrict__ args,
+                                                           int region, int conditional,
+                                                           int mode_bit) {
+    const EigArgs a = args[blockIdx.x];
+    if (conditional && !(a.flags[0] & 4)) return;  // uniform over the workgroup
+    eig_body<JP>(a, region);
+    if (conditional) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.flags[0] &= ~4;
+            a.flags[1] |= mode_bit;
+        }
+    }
+}
+
+size_t eig_lds_bytes(int J) {
+    return ((size_t)eig_region_doubles(J) + eig_small_doubles(J)) * sizeof(double);
+}
+
+int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditional,
+                       int mode_bit, hipStream_t st) {
+    if (jmax > 128) return fail(TK_ERR_UNSUPPORTED, "batched eigensolver: extent %d > 128", jmax);
+    // every problem uses the J = 128 register layout's launch shape; the LDS
+    // partition follows each problem's own J (region computed per J <= jmax)
+    const int region = (int)eig_region_doubles(jmax);
+    const size_t lds = ((size_t)region + eig_small_doubles(jmax)) * sizeof(double);
+    auto fn = eig_batched<128>;
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(fn, dim3(count), dim3(kEigThreads), lds, st, args_dev, region, conditional,
+                       mode_bit);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
 }
 
 int launch_eig(const EigArgs& a, hipStream_t st) {

@@ -275,6 +275,80 @@ int launch_gram_reduce(const double* partial, const GramPlan& pl, int J, double*
     return TK_OK;
 }
 
+// One launch reduces the partials of every problem of a batch (and forms the
+// trace of those that need ||X||^2), in the same fixed order as gram_reduce.
+__global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask* __restrict__ tasks,
+                                                           int ntasks) {
+    __shared__ double part[4][64];
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].wg_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const BatchReduceTask tk = tasks[lo];
+    const int w = blockIdx.x - tk.wg_begin;
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int n = tk.npairs * 256;
+    if (w < tk.nwg - 1 || tk.nu == nullptr) {
+        const int idx = w * 64 + o;
+        double acc = 0.0;
+        if (idx < n)
+            for (int q = g; q < tk.P; q += 4) acc += tk.partial[(int64_t)q * n + idx];
+        part[g][o] = acc;
+        __syncthreads();
+        if (g != 0 || idx >= n) return;
+        const double tot = ((part[0][o] + part[1][o]) + part[2][o]) + part[3][o];
+        const int p = idx >> 8, e = idx & 255;
+        int bi, bj;
+        pair_of(p, tk.nb, bi, bj);
+        const int r = bi * 16 + (e >> 4), c = bj * 16 + (e & 15);
+        if (r >= tk.J || c >= tk.J) return;
+        if (bi == bj && r > c) return;
+        tk.s[r + (int64_t)tk.J * c] = tot;
+        tk.s[c + (int64_t)tk.J * r] = tot;
+    } else {
+        // the problem's last workgroup: trace of its diagonal from the partials
+        // (diagonal 16-blocks p = bi nb - bi (bi - 1) / 2), fixed order
+        if (threadIdx.x < 64) {
+            double acc = 0.0;
+            for (int i = o; i < tk.J; i += 64) {
+                const int bi = i >> 4, p = bi * tk.nb - bi * (bi - 1) / 2;
+                const int idx = p * 256 + (i & 15) * 17;
+                double d = 0.0;
+                for (int q = 0; q < tk.P; ++q) d += tk.partial[(int64_t)q * n + idx];
+                acc += d;
+            }
+            part[0][o] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < 64; ++k) t += part[0][k];
+            *tk.nu = t;
+        }
+    }
+}
+
+// Clears status words with a kernel (no memset node in a captured graph).
+__global__ void fill_i32(int* __restrict__ p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int launch_fill_i32(int* p, int n, int v, hipStream_t st) {
+    if (n <= 0) return TK_OK;
+    hipLaunchKernelGGL(fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+int launch_gram_reduce_batched(const BatchReduceTask* tasks_dev, int ntasks, int total_wg,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(gram_reduce_batched, dim3(total_wg), dim3(256), 0, st, tasks_dev, ntasks);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
                 double* sumsq, void* ws, size_t ws_bytes, hipStream_t st) {
     GramPlan pl = plan_gram(v, precision, (int)dtype_size(dtype));

@@ -29,6 +29,8 @@
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulation, FP32 output).  When the
 // columns are contiguous (mode 1) every lane loads its eight consecutive
 // rows straight from HBM, no LDS staging needed.
+#include <algorithm>
+
 #include "tk_common.hpp"
 
 namespace tk {
@@ -230,11 +232,15 @@ constexpr size_t mx_buf_bytes() {
 // Every 32-block pair of the workgroup's pair group has one owner wave
 // (pair g0 + wave + 8 q, q < NPW), which sees every column of every tile, so
 // each output lives in exactly one wave's registers.
+//
+// The body processes tiles [t0, t1) of pair group `group` and writes its
+// partial (npairs16 x 256 doubles) to `out`; the single-tensor kernel and the
+// batched kernel differ only in how they find those.
 template <int JB, int KT, int NPW, int MODE>
-__global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
-    const float* __restrict__ y, TileMap tm, int npairs32, int pairs_per_group, int npairs16,
-    double* __restrict__ partial) {
-    extern __shared__ double lds_raw[];
+__device__ __forceinline__ void gram_bf16s_body(
+    const float* __restrict__ y, const TileMap& tm, int npairs32, int pairs_per_group,
+    int npairs16, int group, int64_t t0, int64_t t1, double* __restrict__ out,
+    double* lds_raw) {
     using Ld = SplitTile<JB, KT, MODE>;
     constexpr int PK = Ld::PK;
     constexpr int PLANE = JB * PK;
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, kh = lane >> 5;
-    const int g0 = blockIdx.y * pairs_per_group;
+    const int g0 = group * pairs_per_group;
 
     int bi[NPW], bj[NPW], aoff[NPW], boff[NPW];
     bool act[NPW];
@@ -266,8 +272,6 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
         for (int v = 0; v < 16; ++v) accd[q][v] = 0.0;
     }
 
-    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
-    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
     char* base = (char*)lds_raw;
     auto hi_of = [&](int b) { return (__bf16*)(base + b * BUF); };
     auto ex_of = [&](int b) { return (int*)(base + b * BUF + 2 * PLANE * sizeof(__bf16)); };
@@ -325,7 +329,6 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
         __syncthreads();
     }
 
-    double* out = partial + (int64_t)blockIdx.x * npairs16 * 256;
     constexpr int NB16 = 2 * NB;
 #pragma unroll
     for (int q = 0; q < NPW; ++q) {
@@ -340,6 +343,18 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
             out[(int64_t)p16 * 256 + (gi & 15) * 16 + (gj & 15)] = accd[q][v];
         }
     }
+}
+
+template <int JB, int KT, int NPW, int MODE>
+__global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
+    const float* __restrict__ y, TileMap tm, int npairs32, int pairs_per_group, int npairs16,
+    double* __restrict__ partial) {
+    extern __shared__ double lds_raw[];
+    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    gram_bf16s_body<JB, KT, NPW, MODE>(y, tm, npairs32, pairs_per_group, npairs16, blockIdx.y,
+                                      t0, t1, partial + (int64_t)blockIdx.x * npairs16 * 256,
+                                      lds_raw);
 }
 
 // Static schedule per padded extent: tile width, pairs per wave, pair groups
@@ -421,6 +436,73 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
     return mx_launch<JB, kStrided>(y, tm, pl, partial, st);
 }
 
+// ---- batches: one launch covers every problem of a batch ----------------
+__device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, int ntasks,
+                                            int wg) {
+    int lo = 0, hi = ntasks - 1;  // last task with wg_begin <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const BatchView* vm = (const BatchView*)((const char*)v0 + (size_t)mid * stride);
+        if (vm->wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int JB>
+__global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
+    const BatchGramTask* __restrict__ tasks, int ntasks) {
+    extern __shared__ double lds_raw[];
+    constexpr MxGramShape gs = mx_gram_shape<JB>();
+    const int ti = find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x);
+    const BatchGramTask tk = tasks[ti];
+    const int w = blockIdx.x - tk.v.wg_begin;
+    const ModeView mv = batch_mode_view(tk.v);
+    const TileMap tm = make_tiles(mv, gs.KT);
+    const int64_t t0 = tm.ntiles * (int64_t)w / tk.v.nwg;
+    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / tk.v.nwg;
+    constexpr int nb32 = JB / 32, np32 = nb32 * (nb32 + 1) / 2, np16 = 2 * nb32 * (2 * nb32 + 1) / 2;
+    double* out = tk.partial + (int64_t)w * np16 * 256;
+    if (mv.L == 1)
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kUnit>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+    else if (mv.L % 8 == 0 && ((uintptr_t)tk.y & 15) == 0)
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kContig>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+    else
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kStrided>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+}
+
+int mx_gram_kt(int jb) {
+    switch (jb) {
+        case 32: return mx_gram_shape<32>().KT;
+        case 64: return mx_gram_shape<64>().KT;
+        case 128: return mx_gram_shape<128>().KT;
+        case 256: return mx_gram_shape<256>().KT;
+        default: return mx_gram_shape<512>().KT;
+    }
+}
+
+template <int JB>
+static int launch_bf16s_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
+                                  hipStream_t st) {
+    static_assert(mx_gram_shape<JB>().G == 1, "batches need a single pair group");
+    auto fn = gram_bf16s_batched<JB>;
+    const size_t lds = 2 * mx_buf_bytes<JB, mx_gram_shape<JB>().KT>();
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kMxThreads), lds, st, tasks, ntasks);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+                              hipStream_t st) {
+    switch (jb) {
+        case 32: return launch_bf16s_batched_t<32>(tasks_dev, ntasks, total_wg, st);
+        case 64: return launch_bf16s_batched_t<64>(tasks_dev, ntasks, total_wg, st);
+        case 128: return launch_bf16s_batched_t<128>(tasks_dev, ntasks, total_wg, st);
+        default: return fail(TK_ERR_UNSUPPORTED, "batched split Gram: extent class %d", jb);
+    }
+}
+
 int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
                       hipStream_t st) {
     switch (mx_round_jb(v.J)) {
@@ -441,13 +523,14 @@ constexpr int kMtWaves = kMtThreads / 64;
 // NKB: 16-row blocks of op(M) per workgroup; NKS: 32-wide k-steps over J;
 // X3: split both operands (three products) instead of one bf16 product.
 // UNIT: columns contiguous (L == 1, J % 8 == 0), loaded as 16-byte vectors.
+// The body stages rows [r0, r0 + 16 NKB) of op(M) and walks column blocks
+// wg, wg + nwg, ... (one block of 16 columns per wave at a time).
 template <int NKB, int NKS, bool X3, bool UNIT>
-__global__ __launch_bounds__(kMtThreads) void ttm_bf16_kernel(
+__device__ __forceinline__ void ttm_bf16_body(
     const float* __restrict__ y, int64_t L, int64_t ncols, int J, const double* __restrict__ m,
-    int64_t ldm, int K, int transpose, float* __restrict__ z) {
-    __shared__ bf8_t afr[NKB * NKS * 2][64];  // [(kb * NKS + ks) * 2 + hi/lo][lane]
+    int64_t ldm, int K, int transpose, float* __restrict__ z, int r0, int64_t wg, int64_t nwg,
+    bf8_t (*afr)[64]) {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int r0 = blockIdx.y * NKB * 16;
 
     // A fragments: lane l holds op(M)[r0 + 16 kb + l % 16][32 ks + 8 (l / 16) + e].
     for (int f = tid; f < NKB * NKS * 64; f += kMtThreads) {
@@ -472,9 +555,9 @@ __global__ __launch_bounds__(kMtThreads) void ttm_bf16_kernel(
 
     const int c16 = lane & 15, g4 = lane >> 4;
     const int64_t nblk = (ncols + 15) / 16;
-    const int64_t wstride = (int64_t)gridDim.x * kMtWaves;
+    const int64_t wstride = nwg * kMtWaves;
     const int64_t JL = (int64_t)J * L, KL = (int64_t)K * L;
-    for (int64_t cb = (int64_t)blockIdx.x * kMtWaves + (tid >> 6); cb < nblk; cb += wstride) {
+    for (int64_t cb = wg * kMtWaves + (tid >> 6); cb < nblk; cb += wstride) {
         const int64_t col = cb * 16 + c16;
         const bool cv = col < ncols;
         int64_t b = 0, l = 0;
@@ -550,6 +633,15 @@ __global__ __launch_bounds__(kMtThreads) void ttm_bf16_kernel(
     }
 }
 
+template <int NKB, int NKS, bool X3, bool UNIT>
+__global__ __launch_bounds__(kMtThreads) void ttm_bf16_kernel(
+    const float* __restrict__ y, int64_t L, int64_t ncols, int J, const double* __restrict__ m,
+    int64_t ldm, int K, int transpose, float* __restrict__ z) {
+    __shared__ bf8_t afr[NKB * NKS * 2][64];  // [(kb * NKS + ks) * 2 + hi/lo][lane]
+    ttm_bf16_body<NKB, NKS, X3, UNIT>(y, L, ncols, J, m, ldm, K, transpose, z,
+                                      blockIdx.y * NKB * 16, blockIdx.x, gridDim.x, afr);
+}
+
 template <int NKB, int NKS, bool X3>
 static int mt_launch(const float* y, const ModeView& v, const double* m, int64_t ldm, int K,
                      int transpose, float* z, hipStream_t st) {
@@ -597,6 +689,59 @@ static int mt_dispatch(const float* y, const ModeView& v, const double* m, int64
     if (nks <= 8) return mt_pick_kb<8, X3>(y, v, m, ldm, K, transpose, z, st);
     if (nks <= 16) return mt_pick_kb<16, X3>(y, v, m, ldm, K, transpose, z, st);
     return fail(TK_ERR_UNSUPPORTED, "mode extent %d exceeds %d", v.J, TK_MAX_MODE_DIM);
+}
+
+template <int NKB, int NKS, bool X3>
+__global__ __launch_bounds__(kMtThreads) void ttm_bf16_batched(const BatchTtmTask* __restrict__ tasks,
+                                                             int ntasks) {
+    __shared__ bf8_t afr[NKB * NKS * 2][64];
+    const int ti = find_task_wg(&tasks[0].v, sizeof(BatchTtmTask), ntasks, blockIdx.x);
+    const BatchTtmTask tk = tasks[ti];
+    const int w = blockIdx.x - tk.v.wg_begin;
+    const ModeView mv = batch_mode_view(tk.v);
+    const int K = (int)tk.v.ranks[tk.v.n];  // this mode's rank, decided on the device
+    const int r0 = blockIdx.y * NKB * 16;
+    if (r0 >= K) return;                     // row groups beyond the rank: nothing to do
+    const int64_t ncols = mv.L * mv.B;
+    const bool unit = mv.L == 1 && mv.J % 8 == 0 && ((uintptr_t)tk.y & 15) == 0 &&
+                      ((uintptr_t)tk.z & 15) == 0;
+    if (unit)
+        ttm_bf16_body<NKB, NKS, X3, true>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z, r0, w,
+                                          tk.v.nwg, afr);
+    else
+        ttm_bf16_body<NKB, NKS, X3, false>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z, r0, w,
+                                           tk.v.nwg, afr);
+}
+
+template <int NKB, int NKS, bool X3>
+static int launch_ttm_batched_t(const BatchTtmTask* tasks, int ntasks, int total_wg, int kmax,
+                                hipStream_t st) {
+    const int G = (kmax + NKB * 16 - 1) / (NKB * 16);  // row groups up to the rank capacity
+    hipLaunchKernelGGL((ttm_bf16_batched<NKB, NKS, X3>), dim3(total_wg, G), dim3(kMtThreads), 0,
+                       st, tasks, ntasks);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+template <bool X3>
+static int ttm_batched_nks(const BatchTtmTask* tasks, int ntasks, int total_wg, int J, int kmax,
+                           hipStream_t st) {
+    const int nks = (J + 31) / 32, nkb = std::min(4, (kmax + 15) / 16);
+    if (nks > 4) return fail(TK_ERR_UNSUPPORTED, "batched TTM: extent %d too large", J);
+#define TK_TTM_B(KB, KS)                                                            \
+    if (nkb <= KB && nks <= KS)                                                     \
+        return launch_ttm_batched_t<KB, KS, X3>(tasks, ntasks, total_wg, kmax, st)
+    TK_TTM_B(1, 1); TK_TTM_B(1, 2); TK_TTM_B(1, 4);
+    TK_TTM_B(2, 1); TK_TTM_B(2, 2); TK_TTM_B(2, 4);
+    TK_TTM_B(4, 1); TK_TTM_B(4, 2); TK_TTM_B(4, 4);
+#undef TK_TTM_B
+    return fail(TK_ERR_UNSUPPORTED, "batched TTM: no tile");
+}
+
+int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
+                            int kmax, int precision, hipStream_t st) {
+    if (precision == TK_TTM_BF16X3) return ttm_batched_nks<true>(tasks_dev, ntasks, total_wg, J, kmax, st);
+    return ttm_batched_nks<false>(tasks_dev, ntasks, total_wg, J, kmax, st);
 }
 
 int launch_ttm_mixed(const float* y, const ModeView& v, const double* m, int64_t K, int64_t ldm,

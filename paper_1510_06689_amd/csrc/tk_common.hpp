@@ -54,7 +54,7 @@ struct ModeView {
     int J;
 };
 
-inline ModeView mode_view(const int64_t* dims, int ndim, int n) {
+__host__ __device__ inline ModeView mode_view(const int64_t* dims, int ndim, int n) {
     ModeView v{1, 1, (int)dims[n]};
     for (int k = 0; k < n; ++k) v.L *= dims[k];
     for (int k = n + 1; k < ndim; ++k) v.B *= dims[k];
@@ -75,7 +75,7 @@ struct TileMap {
     int64_t ntiles;
 };
 
-inline TileMap make_tiles(const ModeView& v, int KT) {
+__host__ __device__ inline TileMap make_tiles(const ModeView& v, int KT) {
     TileMap t{};
     t.L = v.L;
     t.B = v.B;
@@ -190,6 +190,56 @@ constexpr double kSplitGramGuard = 8.0 / 1073741824.0;
 constexpr double kSplitTtmFloor = 8.0 / 17179869184.0;
 size_t eig_scratch_doubles(int J);
 int launch_eig(const EigArgs& a, hipStream_t st);
+size_t eig_lds_bytes(int J);
+int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditional,
+                       int mode_bit, hipStream_t st);
+
+// ------------------------------------------------------------- batches
+// Device-resident task tables of a batch (one entry per problem and mode
+// step).  The shapes of later modes depend on ranks found on the device, so
+// every workgroup derives its problem's current view from `ranks`: modes in
+// `done` have extent ranks[m], the others their original extent.
+struct BatchView {
+    int64_t dims[TK_MAX_NDIM];
+    const int64_t* ranks;  // device, ndim entries
+    int ndim, n, done;
+    int wg_begin, nwg;     // this problem's workgroups in the launch
+};
+
+__host__ __device__ inline ModeView batch_mode_view(const BatchView& b) {
+    int64_t cur[TK_MAX_NDIM];
+    for (int m = 0; m < b.ndim; ++m) cur[m] = ((b.done >> m) & 1) ? b.ranks[m] : b.dims[m];
+    return mode_view(cur, b.ndim, b.n);
+}
+
+struct BatchGramTask {
+    BatchView v;
+    const float* y;
+    double* partial;  // nwg partial slots
+};
+struct BatchTtmTask {
+    BatchView v;
+    const float* y;
+    const double* u;  // factor, I_n x R_n column-major (ld I_n)
+    float* z;
+};
+struct BatchReduceTask {
+    const double* partial;
+    double* s;
+    double* nu;  // trace target or nullptr
+    int P, npairs, nb, J;
+    int wg_begin, nwg;
+};
+
+int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+                              hipStream_t st);
+int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
+                            int kmax, int precision, hipStream_t st);
+int launch_gram_reduce_batched(const BatchReduceTask* tasks_dev, int ntasks, int total_wg,
+                               hipStream_t st);
+int mx_gram_kt(int jb);   // tile width of the split Gram for a padded extent
+int launch_fill_i32(int* p, int n, int v, hipStream_t st);
+int check_ws(void* ws, size_t ws_bytes, size_t need, const char* what);
 
 int launch_error_metrics(const void* x, const void* xh, int dtype, int64_t n, double* partial,
                          int nblocks, double* out3, hipStream_t st);

@@ -36,7 +36,9 @@ STATUS = {0: "TK_OK", -1: "TK_ERR_INVALID_ARG", -2: "TK_ERR_UNSUPPORTED",
 
 EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "ttm_mode_n", "sthosvd_compress",
            "sthosvd_workspace_bytes", "tucker_reconstruct", "reconstruct_workspace_bytes",
-           "tucker_error_metrics", "error_metrics_workspace_bytes", "tk_status_string",
+           "tucker_error_metrics", "error_metrics_workspace_bytes",
+           "sthosvd_batch_workspace_bytes", "sthosvd_batch_create", "sthosvd_batch_run",
+           "sthosvd_batch_finish", "sthosvd_batch_destroy", "tk_status_string",
            "tk_last_error")
 
 
@@ -64,6 +66,19 @@ class Tucker(ctypes.Structure):
                 ("ranks", ctypes.c_int64 * MAX_NDIM), ("discarded", ctypes.c_double * MAX_NDIM),
                 ("norm2", ctypes.c_double), ("fp64_modes", ctypes.c_uint32),
                 ("ttm_precision_used", ctypes.c_int32)]
+
+
+class BatchOutputs(ctypes.Structure):
+    _fields_ = [("core_dev", ctypes.POINTER(ctypes.c_void_p)),
+                ("core_capacity", ctypes.POINTER(ctypes.c_int64)),
+                ("factors_dev", ctypes.POINTER(ctypes.c_void_p)),
+                ("ranks_dev", ctypes.c_void_p), ("discarded_dev", ctypes.c_void_p),
+                ("norm2_dev", ctypes.c_void_p), ("status_dev", ctypes.c_void_p)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("gram_tiles_per_wg", ctypes.c_int32 * MAX_NDIM),
+                ("ttm_blocks_per_wg", ctypes.c_int32 * MAX_NDIM)]
 
 
 _lib = None
@@ -94,6 +109,13 @@ def library() -> ctypes.CDLL:
         "tucker_error_metrics": (_int, [_pshape, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                         _vp, _sz, _vp]),
         "error_metrics_workspace_bytes": (_sz, [_pshape]),
+        "sthosvd_batch_workspace_bytes": (_sz, [_int, _pshape, ctypes.POINTER(Options)]),
+        "sthosvd_batch_create": (_int, [_int, _pshape, ctypes.POINTER(_vp), ctypes.POINTER(Options),
+                                        ctypes.POINTER(BatchTuning), ctypes.POINTER(BatchOutputs),
+                                        _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+        "sthosvd_batch_run": (_int, [_vp, _vp]),
+        "sthosvd_batch_finish": (_int, [_vp, _vp]),
+        "sthosvd_batch_destroy": (None, [_vp]),
         "tk_status_string": (ctypes.c_char_p, [_int]),
         "tk_last_error": (ctypes.c_char_p, []),
     }
@@ -384,3 +406,171 @@ def error_metrics(x: torch.Tensor, xhat: torch.Tensor):
 def compression_ratio(dims, ranks) -> float:
     """``prod I_n / (prod R_n + sum I_n R_n)`` (Sec. VII-B)."""
     return math.prod(dims) / (math.prod(ranks) + sum(i * r for i, r in zip(dims, ranks)))
+
+
+class BatchCompressor:
+    """ST-HOSVD of many independent FP32 tensors in one launch sequence per
+    mode step (the batched C-ABI).  ``run()`` only enqueues work and may be
+    captured into a HIP graph (``capture()``); ``finish()`` synchronises and
+    redoes any problem whose rank the split Gram could not certify."""
+
+    def __init__(self, xs, eps: float, order=None, ranks=None, max_ranks=None,
+                 ttm_precision: str = "bf16x3", tuning=None):
+        lib = library()
+        self.xs = list(xs)
+        if not self.xs:
+            raise ValueError("empty batch")
+        for x in self.xs:
+            _require_device(x)
+        dev = self.xs[0].device
+        self.device = dev
+        b = len(self.xs)
+        n = self.xs[0].dim()
+        self.ndim = n
+        self._keep = []
+        self.opt = _options(n, eps, order, ranks, max_ranks, "split_bf16", ttm_precision,
+                            self._keep)
+        self.shapes = (Shape * b)()
+        for i, x in enumerate(self.xs):
+            self.shapes[i] = shape_of(x)
+        need = lib.sthosvd_batch_workspace_bytes(b, self.shapes, ctypes.byref(self.opt))
+        if need == 0:
+            h = _vp()
+            _check(lib.sthosvd_batch_create(b, self.shapes, None, ctypes.byref(self.opt), None,
+                                            None, None, 0, None, ctypes.byref(h)))
+        self.dims = [tuple(int(d) for d in x.shape) for x in self.xs]
+        caps = []
+        for d in self.dims:
+            c = list(d)
+            if max_ranks is not None:
+                c = [min(ci, int(m)) for ci, m in zip(c, max_ranks)]
+            if ranks is not None:
+                c = [min(ci, int(r)) for ci, r in zip(c, ranks)]
+            caps.append(c)
+        self.core_bufs = [torch.empty(math.prod(c), dtype=torch.float32, device=dev) for c in caps]
+        self.factor_bufs = [[torch.empty(di * di, dtype=torch.float64, device=dev) for di in d]
+                            for d in self.dims]
+        self.ranks_dev = torch.zeros(b * n, dtype=torch.int64, device=dev)
+        self.disc_dev = torch.zeros(b * n, dtype=torch.float64, device=dev)
+        self.norm2_dev = torch.zeros(b, dtype=torch.float64, device=dev)
+        self.status_dev = torch.zeros(2 * b, dtype=torch.int32, device=dev)
+        self._cores = (_vp * b)(*[t.data_ptr() for t in self.core_bufs])
+        self._caps = (_i64 * b)(*[t.numel() for t in self.core_bufs])
+        facs = (_vp * (b * MAX_NDIM))()
+        for i, fl in enumerate(self.factor_bufs):
+            for k, f in enumerate(fl):
+                facs[i * MAX_NDIM + k] = f.data_ptr()
+        self._facs = facs
+        self.outs = BatchOutputs(self._cores, self._caps, self._facs, self.ranks_dev.data_ptr(),
+                                 self.disc_dev.data_ptr(), self.norm2_dev.data_ptr(),
+                                 self.status_dev.data_ptr())
+        self.tuning = BatchTuning()
+        if tuning is not None:
+            g, t = tuning
+            for k in range(min(len(g), MAX_NDIM)):
+                self.tuning.gram_tiles_per_wg[k] = int(g[k])
+            for k in range(min(len(t), MAX_NDIM)):
+                self.tuning.ttm_blocks_per_wg[k] = int(t[k])
+        self.ws = _workspace(need, dev)
+        xp = (_vp * b)(*[x.data_ptr() for x in self.xs])
+        self._xp = xp
+        h = _vp()
+        _check(lib.sthosvd_batch_create(b, self.shapes, xp, ctypes.byref(self.opt),
+                                        ctypes.byref(self.tuning), ctypes.byref(self.outs),
+                                        _aligned(self.ws), need, _stream(dev), ctypes.byref(h)))
+        self.handle = h
+        self.graph = None
+
+    def run(self, stream=None) -> None:
+        s = _stream(self.device) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(library().sthosvd_batch_run(self.handle, s))
+
+    def capture(self):
+        """Capture one run() into a HIP graph (torch.cuda.CUDAGraph) for replay()."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.run(stream=s)          # warm-up outside the capture
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.run(stream=s)
+        self.graph = g
+        return g
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    def finish(self) -> None:
+        _check(library().sthosvd_batch_finish(self.handle, _stream(self.device)))
+
+    def results(self):
+        n = self.ndim
+        ranks = self.ranks_dev.view(-1, n).cpu().tolist()
+        disc = self.disc_dev.view(-1, n).cpu().tolist()
+        norm2 = self.norm2_dev.cpu().tolist()
+        status = self.status_dev.view(-1, 2).cpu().tolist()
+        out = []
+        for i, d in enumerate(self.dims):
+            r = tuple(int(v) for v in ranks[i])
+            core = self.core_bufs[i][:math.prod(r)].view(tuple(reversed(r))).permute(
+                *reversed(range(n)))
+            facs = [self.factor_bufs[i][k][:d[k] * r[k]].view(r[k], d[k]).t() for k in range(n)]
+            out.append(TuckerTensor(core, facs, r, [], tuple(disc[i]), float(norm2[i]),
+                                    tuple(k for k in range(n) if status[i][1] >> k & 1),
+                                    _TTM_NAMES[int(self.opt.ttm_precision)]))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                library().sthosvd_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def autotune_batch(xs, eps, candidates_gram=(8, 16, 32, 64), candidates_ttm=(16, 64, 256),
+                   reps: int = 5, **kw):
+    """Project autotuner for the batched path: per mode step, picks the Gram
+    tiles-per-workgroup and TTM blocks-per-workgroup that minimise the time of
+    a whole batch run (coordinate search, graph replays timed with events).
+    Returns (gram_tiles_per_wg, ttm_blocks_per_wg) for BatchCompressor."""
+    n = xs[0].dim()
+    g = [16] * n
+    t = [64] * n
+
+    def timed(gv, tv):
+        c = BatchCompressor(xs, eps, tuning=(gv, tv), **kw)
+        c.capture()
+        c.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c.replay()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    best = timed(g, t)
+    for s in range(n):
+        for cand in candidates_gram:
+            if cand == g[s]:
+                continue
+            trial = list(g)
+            trial[s] = cand
+            ms = timed(trial, t)
+            if ms < best:
+                best, g = ms, trial
+        for cand in candidates_ttm:
+            if cand == t[s]:
+                continue
+            trial = list(t)
+            trial[s] = cand
+            ms = timed(g, trial)
+            if ms < best:
+                best, t = ms, trial
+    return g, t, best

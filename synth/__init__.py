@@ -33,6 +33,7 @@ import torch
 __all__ = [
     "Workload",
     "WORKLOADS",
+    "batch_workload",
     "planted_tucker",
     "fortran_empty",
     "is_fortran",
@@ -193,3 +194,23 @@ WORKLOADS = {
     "combustion256": Workload("combustion256", (256, 256, 256, 64, 16), (32, 32, 32, 16, 8),
                               0.8, "cosine", 1e-5, "sigma", 1e-4, 5),
 }
+
+
+def batch_workload(count: int = 64, seed: int = 4000, smin: int = 24, smax: int = 96,
+                   nvar: int = 16, ranks=(12, 12, 12, 6), rho: float = 0.6,
+                   noise: float = 1e-5, eps: float = 1e-4):
+    """A batch of uneven combustion-shaped problems: problem t is s^3 x nvar
+    with s drawn uniformly from [smin, smax] (seeded), planted ranks capped by
+    the extents, cosine factors, geometric decay rho, noise as a per-element
+    sigma, generator seed seed + t.  Returns a list of Workload."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(smin, smax + 1, size=count)
+    out = []
+    for t, s in enumerate(sizes):
+        s = int(s)
+        dims = (s, s, s, nvar)
+        rk = tuple(min(r, d) for r, d in zip(ranks, dims))
+        out.append(Workload(f"batch{t}", dims, rk, rho, "cosine", noise, "sigma", eps,
+                            seed + t))
+    return out

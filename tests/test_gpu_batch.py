@@ -1,0 +1,101 @@
+"""Batched compression (one launch sequence per mode step for a whole batch of
+uneven FP32 problems) against the FP64 oracle per problem, graph replays
+against the eager run, and the finishing step's redo of problems whose rank
+the split Gram could not certify."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1510_06689_amd import tucker
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(sizes, ranks, noise=1e-5, seed=30):
+    xs = []
+    for t, s in enumerate(sizes):
+        dims = (s, s, s, 8)
+        rk = tuple(min(r, d) for r, d in zip(ranks, dims))
+        xs.append(synth.planted_tucker(dims, rk, rho=0.6, factor_kind="cosine", noise=noise,
+                                       noise_mode="sigma", seed=seed + t, dtype=torch.float32))
+    return xs
+
+
+def _relerr(xd, res):
+    xh = tucker.reconstruct(res.core, res.factors)
+    e2, _, n2 = tucker.error_metrics(xd, xh)
+    return math.sqrt(e2 / n2)
+
+
+def test_batch_matches_oracle_per_problem():
+    xs = _problems([20, 33, 48, 64, 90], (5, 5, 5, 3))
+    xd = [to_dev(x) for x in xs]
+    c = tucker.BatchCompressor(xd, 1e-4)
+    c.run()
+    c.finish()
+    res = c.results()
+    for x, d, r in zip(xs, xd, res):
+        xh = x.double().numpy()
+        ref = oracle.sthosvd(xh, 1e-4)
+        say(f"batch problem {x.shape}: ranks {r.ranks} oracle {ref.ranks} redone {r.fp64_modes}")
+        assert r.ranks == ref.ranks
+        xr = oracle.reconstruct(ref.core, ref.factors)
+        rel_ref = math.sqrt(float(np.sum((xh - xr) ** 2)) / ref.norm2)
+        rel = _relerr(d, r)
+        assert rel <= 1e-4 and abs(rel - rel_ref) <= 1e-4
+        assert math.isclose(r.norm2, ref.norm2, rel_tol=1e-6)
+        for u in r.factors:
+            ut = u.cpu().numpy()
+            assert np.abs(ut.T @ ut - np.eye(ut.shape[1])).max() <= 1e-12
+
+
+def test_batch_graph_replays_equal_eager_run():
+    xs = [to_dev(x) for x in _problems([24, 40, 57, 96], (6, 6, 6, 3), seed=50)]
+    c = tucker.BatchCompressor(xs, 1e-4)
+    c.run()
+    torch.cuda.synchronize()
+    ref_ranks = c.ranks_dev.clone()
+    nvalid = [math.prod(r) for r in ref_ranks.view(len(xs), -1).cpu().tolist()]
+    ref_cores = [t[:k].clone() for t, k in zip(c.core_bufs, nvalid)]
+    c.capture()
+    for rep in range(3):
+        for t in c.core_bufs:
+            t.zero_()                       # eager work between replays
+        c.ranks_dev.zero_()
+        torch.cuda.synchronize()
+        c.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c.ranks_dev, ref_ranks), rep
+        for a, b, k in zip(c.core_bufs, ref_cores, nvalid):
+            assert torch.equal(a[:k], b), rep
+
+
+def test_batch_redo_keeps_oracle_ranks_where_uncertain():
+    """eps = 1e-3 with the noise of one problem near the threshold: whatever
+    the guard flags is redone by finish(), and every rank equals the oracle's."""
+    xs = _problems([30, 44], (5, 5, 5, 3), seed=70) + \
+        _problems([36], (5, 5, 5, 3), noise=5e-4, seed=90)
+    xd = [to_dev(x) for x in xs]
+    c = tucker.BatchCompressor(xd, 1e-3)
+    c.run()
+    c.finish()
+    for x, r in zip(xs, c.results()):
+        ref = oracle.sthosvd(x.double().numpy(), 1e-3)
+        say(f"problem {x.shape}: ranks {r.ranks} oracle {ref.ranks} redone {r.fp64_modes}")
+        assert r.ranks == ref.ranks
+
+
+def test_batch_rejects_unsupported():
+    x64 = to_dev(synth.random_tensor((10, 10, 10, 4), seed=1))
+    with pytest.raises(tucker.TuckerError) as e:
+        tucker.BatchCompressor([x64], 1e-3)
+    assert e.value.status == -2
+    big = to_dev(synth.random_tensor((130, 4, 4, 2), seed=2, dtype=torch.float32))
+    with pytest.raises(tucker.TuckerError) as e:
+        tucker.BatchCompressor([big], 1e-3)
+    assert e.value.status == -2
