@@ -188,6 +188,63 @@ def profile_kernels(w, dev, stream):
         f"ttm writes {nb // w.dims[0] * res.ranks[0]} bytes per launch")
 
 
+def batch_leg(dev, steps, warmup, tune=True):
+    """64 uneven FP32 problems s^3 x 16, s ~ U{24..96}: the batched path (one
+    graph replay per batch) against the same problems compressed one after
+    another by the single-problem mixed path."""
+    ws = synth.batch_workload()
+    xs = []
+    for w in ws:
+        x = tucker.empty_fortran(w.dims, torch.float32, dev)
+        x.copy_(w.make(dtype=torch.float64, device=dev))
+        xs.append(x)
+    torch.cuda.synchronize()
+    nbytes = sum(x.numel() * x.element_size() for x in xs)
+    eps = ws[0].eps
+    tuning, tuned_ms = None, None
+    if tune:
+        g, t, tuned_ms = tucker.autotune_batch(xs, eps, reps=3)
+        tuning = (g, t)
+        log(f"[batch64] autotuned gram tiles/wg {g}, ttm blocks/wg {t} ({tuned_ms:.3f} ms)")
+    c = tucker.BatchCompressor(xs, eps, tuning=tuning)
+    c.capture()
+    for _ in range(warmup):
+        c.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    c.finish()
+    res = c.results()
+    # the same problems one by one (single-problem mixed path, host sync per mode)
+    comps = [tucker.Compressor(x.shape, x.dtype, dev, eps, gram_precision="split_bf16",
+                               ttm_precision="bf16x3") for x in xs]
+    for cp, x in zip(comps, xs):
+        cp.run(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, steps // 5)
+    for _ in range(reps):
+        for cp, x in zip(comps, xs):
+            cp.run(x)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) / reps * 1e3
+    same = all(r.ranks == cp.result().ranks for r, cp in zip(res, comps))
+    planted = sum(r.ranks == w.ranks for r, w in zip(res, ws))
+    redone = sum(1 for r in res if r.fp64_modes)
+    log(f"[batch64] {len(xs)} problems, {nbytes / 1e9:.3f} GB: batched graph {ms:.3f} ms, "
+        f"one by one {ms_seq:.3f} ms; ranks equal {same}, planted {planted}/{len(xs)}")
+    return {"problems": len(xs), "input_bytes": nbytes, "ms_per_batch": round(ms, 4),
+            "input_gbs": round(nbytes / (ms / 1e3) / 1e9, 2),
+            "ms_one_by_one": round(ms_seq, 4), "speedup_vs_one_by_one": round(ms_seq / ms, 2),
+            "ranks_equal_one_by_one": same, "planted_ranks_recovered": planted,
+            "problems_redone_fp64": redone, "tuning": tuning,
+            "workload": "64 x (s^3 x 16), s ~ U{24..96} seed 4000, ranks <= (12,12,12,6), "
+                        "decay 0.6, cosine factors, noise 1e-5, eps 1e-4, FP32, split-bf16"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +253,8 @@ def main():
     ap.add_argument("--path", choices=["both", "fp64", "mixed"], default="both",
                     help="both: the mixed path is the headline, the FP64 path its reference")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--gram-reps", type=int, default=10)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="counter runs: only the mode-1 split Gram and TTM of the FP32 tensor "
@@ -280,6 +339,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(x, w.eps, head)
+    if not args.no_batch:
+        x = x64 = x32 = None
+        torch.cuda.empty_cache()
+        out["batch64"] = batch_leg(dev, args.steps, args.warmup, tune=not args.no_autotune)
     print(json.dumps(out), flush=True)
 
 

@@ -227,8 +227,8 @@ size_t error_metrics_workspace_bytes(const tk_shape* x);
  * problems may have different extents) compressed together: every mode step
  * of every problem runs in a handful of launches that cover the whole batch
  * (a split-bf16 Gram, its reduction, one eigensolver workgroup per problem,
- * a split-bf16 TTM), with each problem's later shapes derived on the device
- * from the ranks found there.  sthosvd_batch_run therefore enqueues work
+ * the guard's FP64 recomputation, a split-bf16 TTM), with each problem's
+ * later shapes derived on the device from the ranks found there.  sthosvd_batch_run therefore enqueues work
  * without any host synchronisation, allocation or memset: it can be captured
  * into a HIP graph once and replayed.
  *
@@ -237,9 +237,11 @@ size_t error_metrics_workspace_bytes(const tk_shape* x);
  * eps^2/N >= 2^-31 under the eps rule), every problem with the same ndim and
  * mode order, every extent <= 128.
  *
- * A problem whose rank the split Gram could not certify (status bit 4, see
- * TK_GRAM_SPLIT_BF16) is recomputed, with the FP64 fallback of
- * sthosvd_compress, by sthosvd_batch_finish. */
+ * A mode whose rank the split Gram could not certify (the guard of
+ * TK_GRAM_SPLIT_BF16) is recomputed on the device within the same run, as in
+ * sthosvd_compress: after every eigensolver launch, an FP64 Gram, its
+ * reduction and the eigensolver run again for exactly those problems (the
+ * launches cover the batch; workgroups of other problems return at once). */
 typedef struct tk_batch tk_batch; /* opaque host-side plan */
 
 typedef struct tk_batch_outputs {
@@ -250,8 +252,9 @@ typedef struct tk_batch_outputs {
     double* discarded_dev;          /* device [batch * ndim] */
     double* norm2_dev;              /* device [batch] */
     int32_t* status_dev;            /* device [batch * 2]: [0] bit 1 = capacity exceeded,
-                                       bit 2 = rank not certified (redone by finish);
-                                       [1] bit n = mode n redone in FP64 by finish */
+                                       bit 2 = rank not yet certified (cleared by the
+                                       FP64 recomputation within the run);
+                                       [1] bit n = mode n recomputed in FP64 */
 } tk_batch_outputs;
 
 /* Work partition: column tiles per Gram workgroup and 16-column blocks per
@@ -263,7 +266,8 @@ typedef struct tk_batch_tuning {
     int32_t ttm_blocks_per_wg[TK_MAX_NDIM];
 } tk_batch_tuning;
 
-size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt);
+size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt,
+                                     const tk_batch_tuning* tuning /* NULL = defaults */);
 /* Validates, lays out the workspace (device, caller-owned, 256-byte aligned)
  * and uploads the task tables (one synchronous copy).  x_dev[b] and every
  * output pointer are bound into the plan.  *handle receives a host object
@@ -274,8 +278,8 @@ int sthosvd_batch_create(int batch, const tk_shape* shapes, const void* const* x
                          tk_batch** handle);
 /* Enqueues one compression of every problem (no sync, allocation or memset). */
 int sthosvd_batch_run(tk_batch* handle, void* stream);
-/* Synchronises, redoes the problems with status bit 4 set, reports
- * capacity errors (TK_ERR_CAPACITY). */
+/* Synchronises and reports errors: TK_ERR_CAPACITY (a rank above
+ * max_ranks), TK_ERR_NONFINITE (Inf or NaN in a problem). */
 int sthosvd_batch_finish(tk_batch* handle, void* stream);
 void sthosvd_batch_destroy(tk_batch* handle);
 

@@ -7,6 +7,9 @@
 //   reduction        (one launch; step 0 also forms ||X||^2 per problem)
 //   eigensolver      (one workgroup per problem, rank rule and guard on the
 //                     device)
+//   guard redo       (FP64 Gram, reduction and eigensolver again, each
+//                     launch doing work only for the problems whose rank the
+//                     split Gram could not certify)
 //   split-bf16 TTM   (one launch per extent class; each problem's rank read
 //                     from device memory)
 // with each problem's shapes at later steps derived on the device from its
@@ -73,8 +76,7 @@ struct tk_batch {
     std::vector<StepPlan> steps;
     char* tables_dev = nullptr;
     std::vector<double*> lam;  // per problem, sum of extents
-    void* single_ws = nullptr;
-    size_t single_ws_bytes = 0;
+    bool guarded = false;      // rank rule with the split Gram's guard
 };
 
 namespace {
@@ -144,7 +146,6 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         double *partial, *S, *scratch, *lam;
     };
     std::vector<Bufs> bufs(B);
-    size_t single = 0;
     for (int b = 0; b < B; ++b) {
         const tk_shape& sh = shapes[b];
         int64_t capcur[TK_MAX_NDIM];
@@ -176,10 +177,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         bufs[b].S = (double*)c.take((size_t)jmax * jmax * sizeof(double));
         bufs[b].scratch = (double*)c.take(eig_scratch_doubles(jmax) * sizeof(double));
         bufs[b].lam = (double*)c.take((size_t)sumd * sizeof(double));
-        tk_options o1 = *opt;  // the finishing step's single-problem runs
-        single = std::max(single, sthosvd_workspace_bytes(&sh, &o1));
     }
-    void* single_ws = c.take(single);
 
     // task tables: build on the host in one byte array
     std::vector<char> tab;
@@ -219,11 +217,13 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             bv.n = n;
             bv.done = done;
             const void* yin = s == 0 ? (h ? h->x[b] : nullptr) : bufs[b].y[(s - 1) & 1];
-            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial};
+            const int* status = h ? h->status_dev + 2 * b : nullptr;
+            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial, status};
             gt.v.nwg = nwg;
             gclass[jb].push_back(gt);
             BatchReduceTask rt{bufs[b].partial, bufs[b].S,
-                               s == 0 && h ? h->norm2_dev + b : nullptr, nwg, np16, nb16, v.J, 0, 0};
+                               s == 0 && h ? h->norm2_dev + b : nullptr, nwg, np16, nb16, v.J, 0, 0,
+                               status};
             rt.nwg = ceil_div((int64_t)np16 * 256, 64) + (s == 0 ? 1 : 0);
             rt.wg_begin = red_wg;
             red_wg += rt.nwg;
@@ -284,8 +284,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
     if (h) {
         h->steps = steps;
         h->tables_dev = tables_dev;
-        h->single_ws = single_ws;
-        h->single_ws_bytes = single;
+        h->guarded = !opt->fixed_ranks;
         h->lam.resize(B);
         for (int b = 0; b < B; ++b) h->lam[b] = bufs[b].lam;
         *tables = tab;
@@ -297,9 +296,10 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
 
 extern "C" {
 
-size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt) {
+size_t sthosvd_batch_workspace_bytes(int batch, const tk_shape* shapes, const tk_options* opt,
+                                     const tk_batch_tuning* tuning) {
     if (check_batch(batch, shapes, opt) != TK_OK) return 0;
-    return plan_batch(batch, shapes, opt, nullptr, nullptr, nullptr, nullptr);
+    return plan_batch(batch, shapes, opt, tuning, nullptr, nullptr, nullptr);
 }
 
 int sthosvd_batch_create(int batch, const tk_shape* shapes, const void* const* x_dev,
@@ -381,9 +381,21 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
             TK_TRY(launch_gram_bf16s_batched((const BatchGramTask*)(h->tables_dev + g.off),
                                              g.ntasks, g.total_wg, g.jb, st));
         TK_TRY(launch_gram_reduce_batched((const BatchReduceTask*)(h->tables_dev + sp.red_off),
-                                          sp.red_ntasks, sp.red_wg, st));
+                                          sp.red_ntasks, sp.red_wg, 0, st));
         TK_TRY(launch_eig_batched((const EigArgs*)(h->tables_dev + sp.eig_off), h->B, sp.jmax,
                                   0, 0, st));
+        if (h->guarded) {
+            // ranks the split Gram could not certify: FP64 Gram and eigensolver
+            // again for those problems (the others' workgroups exit at once)
+            for (const GramLaunch& g : sp.grams)
+                TK_TRY(launch_gram_f64_batched((const BatchGramTask*)(h->tables_dev + g.off),
+                                               g.ntasks, g.total_wg, g.jb, 1, st));
+            TK_TRY(launch_gram_reduce_batched(
+                (const BatchReduceTask*)(h->tables_dev + sp.red_off), sp.red_ntasks, sp.red_wg,
+                1, st));
+            TK_TRY(launch_eig_batched((const EigArgs*)(h->tables_dev + sp.eig_off), h->B,
+                                      sp.jmax, 1, 1 << h->order[s], st));
+        }
         for (const TtmLaunch& t : sp.ttms)
             TK_TRY(launch_ttm_bf16_batched((const BatchTtmTask*)(h->tables_dev + t.off),
                                            t.ntasks, t.total_wg, t.J, t.kmax,
@@ -395,33 +407,20 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
 int sthosvd_batch_finish(tk_batch* h, void* stream) {
     if (!h) return fail(TK_ERR_INVALID_ARG, "sthosvd_batch_finish: handle NULL");
     hipStream_t st = (hipStream_t)stream;
-    const int B = h->B, N = h->N;
+    const int B = h->B;
     std::vector<int32_t> status(2 * (size_t)B);
     TK_HIP(hipMemcpyAsync(status.data(), h->status_dev, status.size() * sizeof(int32_t),
                           hipMemcpyDeviceToHost, st));
     TK_HIP(hipStreamSynchronize(st));
-    int rc = TK_OK;
+    std::vector<double> norm2(B);
+    TK_HIP(hipMemcpy(norm2.data(), h->norm2_dev, B * sizeof(double), hipMemcpyDeviceToHost));
     for (int b = 0; b < B; ++b) {
-        if (status[2 * b] & 2) rc = fail(TK_ERR_CAPACITY, "sthosvd_batch: problem %d exceeds max_ranks", b);
-        if (!(status[2 * b] & 4)) continue;
-        // the split Gram could not certify a rank of this problem: redo it
-        tk_tucker t{};
-        t.core_dev = h->cores[b];
-        t.core_capacity = h->core_cap[b];
-        for (int n = 0; n < N; ++n) t.factors_dev[n] = h->factors[(size_t)b * TK_MAX_NDIM + n];
-        t.eigvals_dev = h->lam[b];
-        TK_TRY(sthosvd_compress(&h->shapes[b], h->x[b], &h->opt, &t, h->single_ws,
-                                h->single_ws_bytes, stream));
-        int32_t st2[2] = {0, (int32_t)t.fp64_modes};
-        TK_HIP(hipMemcpyAsync(h->ranks_dev + (size_t)b * N, t.ranks, N * sizeof(int64_t),
-                              hipMemcpyHostToDevice, st));
-        TK_HIP(hipMemcpyAsync(h->disc_dev + (size_t)b * N, t.discarded, N * sizeof(double),
-                              hipMemcpyHostToDevice, st));
-        TK_HIP(hipMemcpyAsync(h->norm2_dev + b, &t.norm2, sizeof(double), hipMemcpyHostToDevice, st));
-        TK_HIP(hipMemcpyAsync(h->status_dev + 2 * b, st2, sizeof st2, hipMemcpyHostToDevice, st));
-        TK_HIP(hipStreamSynchronize(st));
+        if (!std::isfinite(norm2[b]))
+            return fail(TK_ERR_NONFINITE, "sthosvd_batch: problem %d holds Inf or NaN", b);
+        if (status[2 * b] & 2)
+            return fail(TK_ERR_CAPACITY, "sthosvd_batch: a rank of problem %d exceeds max_ranks", b);
     }
-    return rc;
+    return TK_OK;
 }
 
 void sthosvd_batch_destroy(tk_batch* h) { delete h; }

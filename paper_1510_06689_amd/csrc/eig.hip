@@ -724,14 +724,18 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
 }
 
 // One workgroup per problem of a batch.  conditional != 0: only problems whose
-// status word has the guard bit (4) run; afterwards the bit is cleared and
-// `mode_bit` is recorded in the problem's second status word.
+// status word has the guard bit (4) run, on their FP64 Gram and without the
+// guard; afterwards the bit is cleared and `mode_bit` is recorded in the
+// problem's second status word.
 template <int JP>
 __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __restrict__ args,
                                                            int region, int conditional,
                                                            int mode_bit) {
-    const EigArgs a = args[blockIdx.x];
-    if (conditional && !(a.flags[0] & 4)) return;  // uniform over the workgroup
+    EigArgs a = args[blockIdx.x];
+    if (conditional) {
+        if (!(a.flags[0] & 4)) return;  // uniform over the workgroup
+        a.guard = 0.0;
+    }
     eig_body<JP>(a, region);
     if (conditional) {
         __syncthreads();

@@ -45,11 +45,12 @@ constexpr int kGramLdsDoubles = 2 * JB * (KT + 1) > kGramWaves * NPW * 256
 
 // NPW: block pairs per wave; KS: waves sharing one pair set, each taking
 // every KS-th k-step.  The waves form kGramWaves / KS groups of NPW pairs.
+// One workgroup's share: tiles [t0, t1) of pair group g0 .. g0 + npg - 1;
+// writes npairs * 256 partial sums at `out` (those of its own pairs).
 template <typename T, int JB, int KT, int NPW, int KS>
-__global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
-    const T* __restrict__ y, TileMap tm, int nb, int npairs, int pairs_per_group,
-    double* __restrict__ partial) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void gram_f64_body(const T* __restrict__ y, const TileMap& tm, int nb,
+                                              int g0, int npg, int64_t t0, int64_t t1,
+                                              double* __restrict__ out, double* lds) {
     constexpr int P = KT + 1;
     constexpr int NG = kGramWaves / KS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -57,8 +58,6 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
 
     for (int e = tid; e < 2 * JB * P; e += kGramThreads) lds[e] = 0.0;
 
-    const int g0 = blockIdx.y * pairs_per_group;
-    const int npg = min(npairs - g0, pairs_per_group);
     const int grp = wave % NG, slice = wave / NG;
     int aoff[NPW], boff[NPW];
 #pragma unroll
@@ -72,9 +71,6 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
     d4_t acc[NPW];
 #pragma unroll
     for (int q = 0; q < NPW; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
-
-    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
-    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
 
     ColumnTile<T, double, JB, KT, kGramThreads> ld;
     ld.setup(tm, tid);
@@ -106,7 +102,6 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
 
     // v_mfma_f64_16x16x4f64 leaves D[row][col] in lane col + 16 * (row % 4),
     // register row / 4, i.e. row = 4 * v + lane / 16, col = lane % 16.
-    double* out = partial + (int64_t)blockIdx.x * npairs * 256;
     if constexpr (KS > 1) {
         double* red = lds;  // [wave][NPW][256]
 #pragma unroll
@@ -141,6 +136,19 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
             }
         }
     }
+}
+
+template <typename T, int JB, int KT, int NPW, int KS>
+__global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
+    const T* __restrict__ y, TileMap tm, int nb, int npairs, int pairs_per_group,
+    double* __restrict__ partial) {
+    extern __shared__ double lds[];
+    const int g0 = blockIdx.y * pairs_per_group;
+    const int npg = min(npairs - g0, pairs_per_group);
+    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    gram_f64_body<T, JB, KT, NPW, KS>(y, tm, nb, g0, npg, t0, t1,
+                                      partial + (int64_t)blockIdx.x * npairs * 256, lds);
 }
 
 // S[r + J c] for the upper block pairs.  Each workgroup reduces 64 outputs;
@@ -278,7 +286,7 @@ int launch_gram_reduce(const double* partial, const GramPlan& pl, int J, double*
 // One launch reduces the partials of every problem of a batch (and forms the
 // trace of those that need ||X||^2), in the same fixed order as gram_reduce.
 __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask* __restrict__ tasks,
-                                                           int ntasks) {
+                                                           int ntasks, int conditional) {
     __shared__ double part[4][64];
     int lo = 0, hi = ntasks - 1;
     while (lo < hi) {
@@ -286,6 +294,7 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
         if (tasks[mid].wg_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
     const BatchReduceTask tk = tasks[lo];
+    if (conditional && !(*tk.status & 4)) return;  // uniform over the workgroup
     const int w = blockIdx.x - tk.wg_begin;
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int n = tk.npairs * 256;
@@ -343,10 +352,57 @@ int launch_fill_i32(int* p, int n, int v, hipStream_t st) {
 }
 
 int launch_gram_reduce_batched(const BatchReduceTask* tasks_dev, int ntasks, int total_wg,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(gram_reduce_batched, dim3(total_wg), dim3(256), 0, st, tasks_dev, ntasks);
+                               int conditional, hipStream_t st) {
+    hipLaunchKernelGGL(gram_reduce_batched, dim3(total_wg), dim3(256), 0, st, tasks_dev, ntasks,
+                       conditional);
     TK_HIP(hipGetLastError());
     return TK_OK;
+}
+
+// FP64 Gram of every problem of a batch (the guard's recomputation when
+// `conditional`).  The partials use the split kernel's layout -- 16-blocks of
+// the padded extent JB, pairs in pair_of order -- so the same reduction
+// tasks apply; pairs in the padding come out zero.
+template <int JB>
+__global__ __launch_bounds__(kGramThreads) void gram_f64_batched(
+    const BatchGramTask* __restrict__ tasks, int ntasks, int conditional) {
+    extern __shared__ double lds[];
+    constexpr GramShape gs = gram_shape<JB>();
+    constexpr int nb = JB / 16, npairs = nb * (nb + 1) / 2;
+    static_assert(gs.per_group >= npairs, "batches need a single pair group");
+    const int ti = find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x);
+    const BatchGramTask tk = tasks[ti];
+    if (conditional && !(*tk.status & 4)) return;  // uniform over the workgroup
+    const int w = blockIdx.x - tk.v.wg_begin;
+    const TileMap tm = make_tiles(batch_mode_view(tk.v), gs.KT);
+    const int64_t t0 = tm.ntiles * (int64_t)w / tk.v.nwg;
+    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / tk.v.nwg;
+    gram_f64_body<float, JB, gs.KT, gs.NPW, gs.KS>(tk.y, tm, nb, 0, npairs, t0, t1,
+                                                   tk.partial + (int64_t)w * npairs * 256, lds);
+}
+
+template <int JB>
+static int launch_f64_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
+                                int conditional, hipStream_t st) {
+    constexpr GramShape gs = gram_shape<JB>();
+    const size_t lds = (size_t)kGramLdsDoubles<JB, gs.KT, gs.NPW> * sizeof(double);
+    auto fn = gram_f64_batched<JB>;
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kGramThreads), lds, st, tasks, ntasks,
+                       conditional);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+int launch_gram_f64_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+                            int conditional, hipStream_t st) {
+    switch (jb) {
+        case 32: return launch_f64_batched_t<32>(tasks_dev, ntasks, total_wg, conditional, st);
+        case 64: return launch_f64_batched_t<64>(tasks_dev, ntasks, total_wg, conditional, st);
+        case 128: return launch_f64_batched_t<128>(tasks_dev, ntasks, total_wg, conditional, st);
+        default: return fail(TK_ERR_UNSUPPORTED, "batched FP64 Gram: extent class %d", jb);
+    }
 }
 
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,

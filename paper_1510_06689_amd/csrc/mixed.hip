@@ -437,17 +437,6 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
 }
 
 // ---- batches: one launch covers every problem of a batch ----------------
-__device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, int ntasks,
-                                            int wg) {
-    int lo = 0, hi = ntasks - 1;  // last task with wg_begin <= wg
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const BatchView* vm = (const BatchView*)((const char*)v0 + (size_t)mid * stride);
-        if (vm->wg_begin <= wg) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <int JB>
 __global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
     const BatchGramTask* __restrict__ tasks, int ntasks) {

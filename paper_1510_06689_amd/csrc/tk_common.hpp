@@ -206,16 +206,40 @@ struct BatchView {
     int wg_begin, nwg;     // this problem's workgroups in the launch
 };
 
+// Unrolled over the maximal order with constant indices, so that a kernel
+// keeps the problem's extents in registers (no private stack array).
 __host__ __device__ inline ModeView batch_mode_view(const BatchView& b) {
-    int64_t cur[TK_MAX_NDIM];
-    for (int m = 0; m < b.ndim; ++m) cur[m] = ((b.done >> m) & 1) ? b.ranks[m] : b.dims[m];
-    return mode_view(cur, b.ndim, b.n);
+    ModeView v{1, 1, 1};
+#pragma unroll
+    for (int m = 0; m < TK_MAX_NDIM; ++m) {
+        if (m < b.ndim) {
+            const int64_t d = ((b.done >> m) & 1) ? b.ranks[m] : b.dims[m];
+            if (m < b.n) v.L *= d;
+            else if (m == b.n) v.J = (int)d;
+            else v.B *= d;
+        }
+    }
+    return v;
+}
+
+// Task of workgroup `wg` in a launch whose tasks (stride bytes apart, each
+// starting with a BatchView) own consecutive workgroup ranges.
+__device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, int ntasks,
+                                            int wg) {
+    int lo = 0, hi = ntasks - 1;  // last task with wg_begin <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const BatchView* vm = (const BatchView*)((const char*)v0 + (size_t)mid * stride);
+        if (vm->wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 struct BatchGramTask {
     BatchView v;
     const float* y;
-    double* partial;  // nwg partial slots
+    double* partial;     // nwg partial slots
+    const int* status;   // the problem's status word (bit 4: rank not certified)
 };
 struct BatchTtmTask {
     BatchView v;
@@ -229,14 +253,19 @@ struct BatchReduceTask {
     double* nu;  // trace target or nullptr
     int P, npairs, nb, J;
     int wg_begin, nwg;
+    const int* status;
 };
 
 int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
                               hipStream_t st);
 int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
                             int kmax, int precision, hipStream_t st);
+// conditional != 0: only problems whose status has bit 4 set take part (the
+// guard's FP64 recomputation); the others' workgroups return at once.
+int launch_gram_f64_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+                            int conditional, hipStream_t st);
 int launch_gram_reduce_batched(const BatchReduceTask* tasks_dev, int ntasks, int total_wg,
-                               hipStream_t st);
+                               int conditional, hipStream_t st);
 int mx_gram_kt(int jb);   // tile width of the split Gram for a padded extent
 int launch_fill_i32(int* p, int n, int v, hipStream_t st);
 int check_ws(void* ws, size_t ws_bytes, size_t need, const char* what);

@@ -109,7 +109,8 @@ def library() -> ctypes.CDLL:
         "tucker_error_metrics": (_int, [_pshape, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                         _vp, _sz, _vp]),
         "error_metrics_workspace_bytes": (_sz, [_pshape]),
-        "sthosvd_batch_workspace_bytes": (_sz, [_int, _pshape, ctypes.POINTER(Options)]),
+        "sthosvd_batch_workspace_bytes": (_sz, [_int, _pshape, ctypes.POINTER(Options),
+                                                ctypes.POINTER(BatchTuning)]),
         "sthosvd_batch_create": (_int, [_int, _pshape, ctypes.POINTER(_vp), ctypes.POINTER(Options),
                                         ctypes.POINTER(BatchTuning), ctypes.POINTER(BatchOutputs),
                                         _vp, _sz, _vp, ctypes.POINTER(_vp)]),
@@ -411,8 +412,9 @@ def compression_ratio(dims, ranks) -> float:
 class BatchCompressor:
     """ST-HOSVD of many independent FP32 tensors in one launch sequence per
     mode step (the batched C-ABI).  ``run()`` only enqueues work and may be
-    captured into a HIP graph (``capture()``); ``finish()`` synchronises and
-    redoes any problem whose rank the split Gram could not certify."""
+    captured into a HIP graph (``capture()``); ranks the split Gram cannot
+    certify are recomputed in FP64 within the run.  ``finish()`` synchronises
+    and raises on capacity or non-finite errors."""
 
     def __init__(self, xs, eps: float, order=None, ranks=None, max_ranks=None,
                  ttm_precision: str = "bf16x3", tuning=None):
@@ -433,7 +435,15 @@ class BatchCompressor:
         self.shapes = (Shape * b)()
         for i, x in enumerate(self.xs):
             self.shapes[i] = shape_of(x)
-        need = lib.sthosvd_batch_workspace_bytes(b, self.shapes, ctypes.byref(self.opt))
+        self.tuning = BatchTuning()
+        if tuning is not None:
+            g, t = tuning
+            for k in range(min(len(g), MAX_NDIM)):
+                self.tuning.gram_tiles_per_wg[k] = int(g[k])
+            for k in range(min(len(t), MAX_NDIM)):
+                self.tuning.ttm_blocks_per_wg[k] = int(t[k])
+        need = lib.sthosvd_batch_workspace_bytes(b, self.shapes, ctypes.byref(self.opt),
+                                                 ctypes.byref(self.tuning))
         if need == 0:
             h = _vp()
             _check(lib.sthosvd_batch_create(b, self.shapes, None, ctypes.byref(self.opt), None,
@@ -464,13 +474,6 @@ class BatchCompressor:
         self.outs = BatchOutputs(self._cores, self._caps, self._facs, self.ranks_dev.data_ptr(),
                                  self.disc_dev.data_ptr(), self.norm2_dev.data_ptr(),
                                  self.status_dev.data_ptr())
-        self.tuning = BatchTuning()
-        if tuning is not None:
-            g, t = tuning
-            for k in range(min(len(g), MAX_NDIM)):
-                self.tuning.gram_tiles_per_wg[k] = int(g[k])
-            for k in range(min(len(t), MAX_NDIM)):
-                self.tuning.ttm_blocks_per_wg[k] = int(t[k])
         self.ws = _workspace(need, dev)
         xp = (_vp * b)(*[x.data_ptr() for x in self.xs])
         self._xp = xp

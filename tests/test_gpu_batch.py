@@ -1,6 +1,6 @@
 """Batched compression (one launch sequence per mode step for a whole batch of
 uneven FP32 problems) against the FP64 oracle per problem, graph replays
-against the eager run, and the finishing step's redo of problems whose rank
+against the eager run, and the in-run FP64 recomputation of modes whose rank
 the split Gram could not certify."""
 import math
 
@@ -77,7 +77,8 @@ def test_batch_graph_replays_equal_eager_run():
 
 def test_batch_redo_keeps_oracle_ranks_where_uncertain():
     """eps = 1e-3 with the noise of one problem near the threshold: whatever
-    the guard flags is redone by finish(), and every rank equals the oracle's."""
+    the guard flags is recomputed within the run, and every rank equals the
+    oracle's."""
     xs = _problems([30, 44], (5, 5, 5, 3), seed=70) + \
         _problems([36], (5, 5, 5, 3), noise=5e-4, seed=90)
     xd = [to_dev(x) for x in xs]
@@ -88,6 +89,37 @@ def test_batch_redo_keeps_oracle_ranks_where_uncertain():
         ref = oracle.sthosvd(x.double().numpy(), 1e-3)
         say(f"problem {x.shape}: ranks {r.ranks} oracle {ref.ranks} redone {r.fp64_modes}")
         assert r.ranks == ref.ranks
+
+
+def test_batch_guard_recomputes_on_device():
+    """Problems of the 64-problem benchmark batch (s^3 x 16, ranks (12,12,12,6),
+    eps = 1e-4): after two truncations the unfoldings' columns decay by rho^r,
+    the split representation error (relative to each row's largest entry)
+    reaches a third of the threshold in the tail sums, and the guard refuses
+    to certify some ranks.  The run must resolve them on the device (no
+    status bit 4 left, recorded per mode), with every rank equal to the
+    oracle's and the error equal to the single-problem path's."""
+    ws = synth.batch_workload()
+    pick = [19, 15, 1]                       # s = 56, 28, 57
+    xs = [ws[i].make(dtype=torch.float64).float() for i in pick]
+    xd = [to_dev(x) for x in xs]
+    eps = ws[0].eps
+    c = tucker.BatchCompressor(xd, eps)
+    c.run()
+    torch.cuda.synchronize()
+    status = c.status_dev.view(-1, 2).cpu().numpy()
+    assert not (status[:, 0] & 4).any(), status
+    c.finish()
+    res = c.results()
+    assert any(r.fp64_modes for r in res), [r.fp64_modes for r in res]
+    for i, x, d, r in zip(pick, xs, xd, res):
+        ref = oracle.sthosvd(x.double().numpy(), eps)
+        single = tucker.sthosvd(d, eps, gram_precision="split_bf16", ttm_precision="bf16x3")
+        say(f"problem {i} {tuple(x.shape)}: ranks {r.ranks} oracle {ref.ranks} "
+            f"fp64 modes batch {r.fp64_modes} single {single.fp64_modes}")
+        assert r.ranks == ref.ranks == ws[i].ranks
+        rel, rel1 = _relerr(d, r), _relerr(d, single)
+        assert rel <= eps and abs(rel - rel1) <= 1e-2 * rel1
 
 
 def test_batch_rejects_unsupported():
