@@ -144,6 +144,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
     struct Bufs {
         void* y[2];
         double *partial, *S, *scratch, *lam;
+        int* nparts;
     };
     std::vector<Bufs> bufs(B);
     for (int b = 0; b < B; ++b) {
@@ -177,6 +178,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         bufs[b].S = (double*)c.take((size_t)jmax * jmax * sizeof(double));
         bufs[b].scratch = (double*)c.take(eig_scratch_doubles(jmax) * sizeof(double));
         bufs[b].lam = (double*)c.take((size_t)sumd * sizeof(double));
+        bufs[b].nparts = (int*)c.take(sizeof(int));
     }
 
     // task tables: build on the host in one byte array
@@ -209,7 +211,8 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int nb16 = 2 * (jb / 32), np16 = nb16 * (nb16 + 1) / 2;
             const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
                                                                : kDefaultGramTilesPerWg;
-            const int nwg = std::max(1, std::min(4096, ceil_div(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw)));
+            const int64_t ntiles = make_tiles(v, mx_gram_kt(jb)).ntiles;
+            const int nwg = std::max(1, std::min(4096, ceil_div(ntiles, tpw)));
             BatchView bv{};
             for (int k = 0; k < N; ++k) bv.dims[k] = sh.dims[k];
             bv.ranks = h ? h->ranks_dev + (size_t)b * N : nullptr;
@@ -218,12 +221,13 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             bv.done = done;
             const void* yin = s == 0 ? (h ? h->x[b] : nullptr) : bufs[b].y[(s - 1) & 1];
             const int* status = h ? h->status_dev + 2 * b : nullptr;
-            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial, status};
+            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial, status, bufs[b].nparts,
+                             ceil_div(ntiles, nwg)};
             gt.v.nwg = nwg;
             gclass[jb].push_back(gt);
             BatchReduceTask rt{bufs[b].partial, bufs[b].S,
                                s == 0 && h ? h->norm2_dev + b : nullptr, nwg, np16, nb16, v.J, 0, 0,
-                               status};
+                               status, bufs[b].nparts};
             rt.nwg = ceil_div((int64_t)np16 * 256, 64) + (s == 0 ? 1 : 0);
             rt.wg_begin = red_wg;
             red_wg += rt.nwg;

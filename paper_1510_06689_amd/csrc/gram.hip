@@ -298,11 +298,12 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
     const int w = blockIdx.x - tk.wg_begin;
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int n = tk.npairs * 256;
+    const int P = *tk.nparts;  // slots the Gram launch wrote (<= tk.P)
     if (w < tk.nwg - 1 || tk.nu == nullptr) {
         const int idx = w * 64 + o;
         double acc = 0.0;
         if (idx < n)
-            for (int q = g; q < tk.P; q += 4) acc += tk.partial[(int64_t)q * n + idx];
+            for (int q = g; q < P; q += 4) acc += tk.partial[(int64_t)q * n + idx];
         part[g][o] = acc;
         __syncthreads();
         if (g != 0 || idx >= n) return;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
                 const int bi = i >> 4, p = bi * tk.nb - bi * (bi - 1) / 2;
                 const int idx = p * 256 + (i & 15) * 17;
                 double d = 0.0;
-                for (int q = 0; q < tk.P; ++q) d += tk.partial[(int64_t)q * n + idx];
+                for (int q = 0; q < P; ++q) d += tk.partial[(int64_t)q * n + idx];
                 acc += d;
             }
             part[0][o] = acc;
@@ -375,8 +376,11 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_batched(
     if (conditional && !(*tk.status & 4)) return;  // uniform over the workgroup
     const int w = blockIdx.x - tk.v.wg_begin;
     const TileMap tm = make_tiles(batch_mode_view(tk.v), gs.KT);
-    const int64_t t0 = tm.ntiles * (int64_t)w / tk.v.nwg;
-    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / tk.v.nwg;
+    const int active = (int)(tm.ntiles < tk.v.nwg ? tm.ntiles : tk.v.nwg);
+    if (w == 0 && threadIdx.x == 0) *tk.nparts = active;
+    if (w >= active) return;  // uniform over the workgroup
+    const int64_t t0 = tm.ntiles * (int64_t)w / active;
+    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / active;
     gram_f64_body<float, JB, gs.KT, gs.NPW, gs.KS>(tk.y, tm, nb, 0, npairs, t0, t1,
                                                    tk.partial + (int64_t)w * npairs * 256, lds);
 }

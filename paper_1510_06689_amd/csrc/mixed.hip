@@ -447,8 +447,13 @@ __global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
     const int w = blockIdx.x - tk.v.wg_begin;
     const ModeView mv = batch_mode_view(tk.v);
     const TileMap tm = make_tiles(mv, gs.KT);
-    const int64_t t0 = tm.ntiles * (int64_t)w / tk.v.nwg;
-    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / tk.v.nwg;
+    // workgroups needed at the actual shape (>= 1: a shape has >= 1 tile)
+    const int64_t need = (tm.ntiles + tk.tpw - 1) / tk.tpw;
+    const int active = (int)(need < tk.v.nwg ? need : tk.v.nwg);
+    if (w == 0 && threadIdx.x == 0) *tk.nparts = active;
+    if (w >= active) return;  // uniform over the workgroup
+    const int64_t t0 = tm.ntiles * (int64_t)w / active;
+    const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / active;
     constexpr int nb32 = JB / 32, np32 = nb32 * (nb32 + 1) / 2, np16 = 2 * nb32 * (2 * nb32 + 1) / 2;
     double* out = tk.partial + (int64_t)w * np16 * 256;
     if (mv.L == 1)

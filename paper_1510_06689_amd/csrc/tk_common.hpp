@@ -62,10 +62,11 @@ __host__ __device__ inline ModeView mode_view(const int64_t* dims, int ndim, int
 }
 
 // Column tiles of KT columns over a ModeView.  Two regimes:
-//  packed  (KT % L == 0): a tile is KT/L consecutive b-blocks, one contiguous
-//          memory range of (KT/L) * J * L elements; column kk = bb * L + l.
-//  strided (otherwise):   a tile is a segment [l0, l0 + KT) of one b-block,
-//          J rows of up to KT contiguous elements with row stride L.
+//  packed  (L <= KT): a tile is nbb = floor(KT / L) consecutive b-blocks, one
+//          contiguous memory range of nbb * J * L elements; column
+//          kk = bb * L + l, and columns nbb * L .. KT - 1 are padding (zero).
+//  strided (L > KT):  a tile is a segment [l0, l0 + KT) of one b-block, J
+//          rows of up to KT contiguous elements with row stride L.
 struct TileMap {
     int64_t L, B;
     int J, KT;
@@ -81,7 +82,7 @@ __host__ __device__ inline TileMap make_tiles(const ModeView& v, int KT) {
     t.B = v.B;
     t.J = v.J;
     t.KT = KT;
-    t.packed = (v.L <= KT && KT % v.L == 0) ? 1 : 0;
+    t.packed = v.L <= KT ? 1 : 0;
     if (t.packed) {
         t.nbb = (int)(KT / v.L);
         t.lsegs = 1;
@@ -235,11 +236,17 @@ __device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, 
     return lo;
 }
 
+// A Gram task owns nwg workgroups (sized for the capacity shape); at run time
+// only as many take part as the actual tiles need (tpw tiles each for the
+// split Gram, at least one tile each for the FP64 Gram), and workgroup 0
+// records that count in *nparts for the reduction.
 struct BatchGramTask {
     BatchView v;
     const float* y;
     double* partial;     // nwg partial slots
     const int* status;   // the problem's status word (bit 4: rank not certified)
+    int* nparts;         // partial slots written by the last Gram launch
+    int tpw;             // split-Gram tiles per workgroup
 };
 struct BatchTtmTask {
     BatchView v;
@@ -251,9 +258,10 @@ struct BatchReduceTask {
     const double* partial;
     double* s;
     double* nu;  // trace target or nullptr
-    int P, npairs, nb, J;
+    int P, npairs, nb, J;  // P: partial slots reserved (the sum runs over *nparts)
     int wg_begin, nwg;
     const int* status;
+    const int* nparts;
 };
 
 int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
