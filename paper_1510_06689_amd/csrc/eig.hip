@@ -75,6 +75,16 @@ __device__ __forceinline__ double recip(double q) {
     return fma(r, err, r);
 }
 
+// 1/sqrt(s) (s > 0 finite) from the hardware estimate refined by two Newton
+// steps r <- r + r (1 - s r^2) / 2.
+__device__ __forceinline__ double rsq(double s) {
+    double r = __builtin_amdgcn_rsq(s);
+    double err = fma(-(s * r), r, 1.0);
+    r = fma(0.5 * r, err, r);
+    err = fma(-(s * r), r, 1.0);
+    return fma(0.5 * r, err, r);
+}
+
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
     uint64_t z = ((uint64_t)a << 32) ^ (uint64_t)b ^ 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -177,12 +187,11 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     if constexpr (JP > 0) {
     // ---- 1. Householder tridiagonalisation, A in registers ---------------
     // Thread t owns row i = t / 8 and the columns j = t % 8 + 8 q.  Per column
-    // k: the owners of row k publish it (= column k), every wave forms the
-    // reflector's scalars from it (same bits everywhere), w = A22 v is a sum
-    // over the row's 8 lanes, p = b w is published, and each thread updates
-    // its own elements.  Vectors alternate between two LDS buffers so that two
-    // barriers per column suffice; reflectors collect in LDS and go to the
-    // global scratch once at the end.
+    // k: the owners of row k form the reflector and publish v; (A22 v)_i is a
+    // sum over the row's 8 lanes and p = tau A22 v is published; each thread
+    // then updates its own elements.  Vectors alternate between two LDS
+    // buffers so that two barriers per column suffice; reflectors collect in
+    // LDS and go to the global scratch once at the end.
     constexpr int NQ = JP / 8;
     const int ri = tid >> 3, rc = tid & 7;
     const bool rowok = ri < J;
@@ -203,80 +212,93 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     for (int i = tid; i < 4 * JP; i += kEigThreads) vbuf[i] = 0.0;
     __syncthreads();
     for (int k = 0; k + 2 < J; ++k) {
-        double* xs = vbuf + (k & 1) * JP;
-        double* ps = vbuf + (2 + (k & 1)) * JP;
-        double* sg = red + 40 + (k & 1);  // sigma of column k
+        double* vs = Hs + (size_t)k * JP;        // v = reflector k: v_{k+1} = 1, zero outside k < j < J
+        double* ps = vbuf + (2 + (k & 1)) * JP;  // p = tau A22 v, zero outside k < i < J
+        double* sg = red + 40 + (k & 1);         // tau of column k
         if (ri == k) {
-            // the owners publish column k and sigma = sum_{j > k+1} x_j^2
-            double sq = 0.0;
+            // The owners of row k (= column k, x = its part beyond the diagonal)
+            // form the reflector alone, in the form of LAPACK's dlarfg:
+            // alpha = -sign(x_0) |x|, tau = 1 + |x_0| / |x|, v = x / (x_0 - alpha)
+            // (one reciprocal square root and one reciprocal), and publish v.
+            double sq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int j = rc + 8 * q;
-                xs[j] = av[q];
-                sq = fma(((j >= k + 2 && j < J) ? 1.0 : 0.0) * av[q], av[q], sq);
+                sq[q & 3] = fma(((j >= k + 2 && j < J) ? 1.0 : 0.0) * av[q], av[q], sq[q & 3]);
             }
-            sq = row8_sum(sq);
-            if (rc == 0) *sg = sq;
-            if ((k & 7) == rc) d[k] = av[k >> 3];
+            const double sigma = row8_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
+            // a_{k,k+1} and a_kk: register (k + 1) / 8 (resp. k / 8) of the
+            // owner lane of their column; both indices are uniform
+            const int lane0 = 8 * (k & 7);
+            const double x0 = read_lane(av[(k + 1) >> 3], lane0 + ((k + 1) & 7));
+            const double akk = read_lane(av[k >> 3], lane0 + (k & 7));
+            double tau = 0.0, alpha = x0, inv_v0 = 0.0;
+            if (sigma != 0.0) {
+                const double ss = fma(x0, x0, sigma);
+                const double r = rsq(ss);  // 1 / |x|
+                const double mu = ss * r;
+                const double sgn = x0 < 0.0 ? -1.0 : 1.0;
+                alpha = -sgn * mu;
+                tau = fma(fabs(x0), r, 1.0);
+                inv_v0 = sgn * recip(fabs(x0) + mu);
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = rc + 8 * q;
+                vs[j] = j == k + 1 ? 1.0 : ((j > k + 1 && j < J) ? av[q] * inv_v0 : 0.0);
+            }
+            if (rc == 0) {
+                *sg = tau;
+                d[k] = akk;
+                e[k] = alpha;
+                beta[k] = tau;
+            }
         }
         __syncthreads();
-        const double sigma = *sg;
-        const double x0 = xs[k + 1];
-        double b, mu, v0;
-        if (sigma == 0.0) {
-            b = 0.0;
-            mu = x0;
-            v0 = 1.0;
-        } else {
-            mu = sqrt(x0 * x0 + sigma);
-            v0 = (x0 <= 0.0) ? x0 - mu : -sigma * recip(x0 + mu);
-            b = 2.0 * v0 * v0 * recip(sigma + v0 * v0);
-        }
-        if (tid == 0) {
-            e[k] = mu;
-            beta[k] = b;
-        }
-        if (b == 0.0) continue;  // uniform: the reflector is the identity
-        const double inv_v0 = recip(v0);
+        const double tau = *sg;
+        if (tau == 0.0) continue;  // uniform: the reflector is the identity
+        // Rows and columns <= k are finished: a wave whose 8 rows are all <= k
+        // has nothing to form or update, nor has column group q (columns
+        // 8q .. 8q + 7) once 8q + 7 <= k.  Both tests are uniform over a wave.
+        const bool wact = 8 * wave + 7 > k;
         double vq[NQ];
-        double pr[4] = {0.0, 0.0, 0.0, 0.0};
+        double part = 0.0;
+        if (wact) {
+            double pr[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int j = rc + 8 * q;
-            const double xj = xs[j];
-            vq[q] = ((j > k && j < J) ? 1.0 : 0.0) * (j == k + 1 ? 1.0 : xj * inv_v0);
-            pr[q & 3] = fma(av[q], vq[q], pr[q & 3]);
+            for (int q = 0; q < NQ; ++q) {
+                vq[q] = 0.0;
+                if (8 * q + 7 > k) {
+                    vq[q] = vs[rc + 8 * q];
+                    pr[q & 3] = fma(av[q], vq[q], pr[q & 3]);
+                }
+            }
+            part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
         }
-        double part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
-        if (rc == 0 && ri > k && rowok) ps[ri] = b * part;
-        if (ri == k) {  // reflector k: Hs[k J + j] = v_j (entries j <= k are never read)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) Hs[(size_t)k * J + rc + 8 * q] = vq[q];
-        }
+        if (rc == 0 && ri < JP) ps[ri] = (wact && ri > k && rowok) ? tau * part : 0.0;
         __syncthreads();
-        // A22 -= v p^T + p v^T - 2 kc v v^T with 2 kc = b p.v (every wave the
-        // same bits), in a commutative form so that A stays exactly symmetric
+        if (!wact) continue;  // uniform over the wave; it still meets every barrier
+        // A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v.  Every wave forms
+        // p.v with the same bits, and w_i, w_j come from the same formula on
+        // the same values, so A stays exactly symmetric; entries outside the
+        // trailing block see v = w = 0.
         double pv = 0.0;
 #pragma unroll
         for (int r = 0; r < NS; ++r) {
             const int j = lane + 64 * r;
-            const int jc = j < JP ? j : 0;
-            const double mj = (j >= k + 1 && j < J) ? 1.0 : 0.0;
-            const double vj = j == k + 1 ? 1.0 : xs[jc] * inv_v0;
-            pv = fma(mj * ps[jc], vj, pv);
+            if (j < JP) pv = fma(ps[j], vs[j], pv);
         }
-        const double kc2 = b * wave_sum(pv);
-        const double mrow = (ri > k && rowok) ? 1.0 : 0.0;
+        const double half = 0.5 * tau * wave_sum(pv);
         const int ric = ri < JP ? ri : 0;
-        const double vi = ri == k + 1 ? 1.0 : xs[ric] * inv_v0;
-        const double pi = ps[ric];
+        const double vi = vs[ric], wi = fma(-half, vi, ps[ric]);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int j = rc + 8 * q;
-            const double vj = vq[q], pj = ps[j];
-            const double t = __dadd_rn(__dmul_rn(vi, pj), __dmul_rn(pi, vj));
-            const double du = __dsub_rn(t, __dmul_rn(kc2, __dmul_rn(vi, vj)));
-            av[q] -= (mrow * ((j > k && j < J) ? 1.0 : 0.0)) * du;
+            if (8 * q + 7 > k) {
+                const int j = rc + 8 * q;
+                const double vj = vq[q];
+                const double wj = fma(-half, vj, ps[j]);
+                av[q] -= __dadd_rn(__dmul_rn(vi, wj), __dmul_rn(wi, vj));
+            }
         }
     }
     // the trailing 2 x 2 block (or 1 x 1)
@@ -296,7 +318,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     __syncthreads();
     for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) {
         const int k = idx / J, i = idx - k * J;
-        if (i < J - k - 1) H[idx] = Hs[idx + k + 1];
+        if (i < J - k - 1) H[idx] = Hs[(size_t)k * JP + k + 1 + i];
     }
     __syncthreads();
     } else {
@@ -436,9 +458,9 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         const double gl = red[32], gu = red[33];
         int jp = 32;
         while (jp < J) jp *= 2;
-        // about 256 active lanes (one wave per SIMD): more sample points per
+        // about 512 active lanes (two waves per SIMD): more sample points per
         // eigenvalue add work faster than they remove iterations
-        const int tpe = jp >= 256 ? 1 : 256 / jp;  // threads (sample points) per eigenvalue
+        const int tpe = jp >= 512 ? 1 : 512 / jp;  // threads (sample points) per eigenvalue
         const int k = tid / tpe, s = tid - (tid / tpe) * tpe;
         const int gofs = (lane / tpe) * tpe;
         const uint64_t gmask = (((1ull << tpe) - 1ull) << gofs);
@@ -746,8 +768,16 @@ __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __rest
     }
 }
 
+// The register path (J <= JP) keeps reflector k at row k, pitch JP, of the
+// region: at least JP * J doubles (<= 16384 for JP <= 128).
+static size_t eig_region_doubles_jp(int J, int JP) {
+    const size_t r = eig_region_doubles(J), hs = (size_t)JP * J;
+    return r < hs ? hs : r;
+}
+
 size_t eig_lds_bytes(int J) {
-    return ((size_t)eig_region_doubles(J) + eig_small_doubles(J)) * sizeof(double);
+    const int JP = J <= 32 ? 32 : J <= 64 ? 64 : J <= 128 ? 128 : 0;
+    return ((size_t)eig_region_doubles_jp(J, JP) + eig_small_doubles(J)) * sizeof(double);
 }
 
 int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditional,
@@ -755,7 +785,7 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
     if (jmax > 128) return fail(TK_ERR_UNSUPPORTED, "batched eigensolver: extent %d > 128", jmax);
     // every problem uses the J = 128 register layout's launch shape; the LDS
     // partition follows each problem's own J (region computed per J <= jmax)
-    const int region = (int)eig_region_doubles(jmax);
+    const int region = (int)eig_region_doubles_jp(jmax, 128);
     const size_t lds = ((size_t)region + eig_small_doubles(jmax)) * sizeof(double);
     auto fn = eig_batched<128>;
     TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -767,7 +797,8 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
 }
 
 int launch_eig(const EigArgs& a, hipStream_t st) {
-    const int region = (int)eig_region_doubles(a.J);
+    const int JP = a.J <= 32 ? 32 : a.J <= 64 ? 64 : a.J <= 128 ? 128 : 0;
+    const int region = (int)eig_region_doubles_jp(a.J, JP);
     const size_t lds = ((size_t)region + eig_small_doubles(a.J)) * sizeof(double);
     if (a.J <= 128) {
         auto fn = a.J <= 32 ? eig_kernel<32> : a.J <= 64 ? eig_kernel<64> : eig_kernel<128>;
