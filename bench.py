@@ -141,14 +141,17 @@ def run_leg(name, x, w, gp, tp, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt / steps * 1e3
-    res = comp.result()
+    res = comp.result(copy=True)  # compact: no reference to the compressor's buffers
     xh = tucker.reconstruct(res.core, res.factors, precision="fp64")
     e2, mx, n2 = tucker.error_metrics(x, xh)
     del xh, comp
     torch.cuda.empty_cache()
     in_bytes = x.numel() * x.element_size()
+    alg = algorithmic_bytes(w.dims, res.ranks, range(len(w.dims)), x.element_size())
     leg = {"ms_per_step": round(ms, 4), "input_gbs": round(in_bytes / (ms / 1e3) / 1e9, 2),
-           "gelem_s": round(x.numel() / (ms / 1e3) / 1e9, 3), "ranks": list(res.ranks),
+           "gelem_s": round(x.numel() / (ms / 1e3) / 1e9, 3),
+           "algorithmic_bytes": alg, "algorithmic_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+           "ranks": list(res.ranks),
            "relerr": math.sqrt(e2 / n2), "max_abs_err": mx, "gram": gp, "ttm": tp,
            "storage": str(x.dtype).replace("torch.", "")}
     log(f"[{name}] {steps} steps: {ms:.3f} ms/step, {leg['input_gbs']} GB/s, ranks {res.ranks},"
@@ -245,6 +248,59 @@ def batch_leg(dev, steps, warmup, tune=True):
                         "decay 0.6, cosine factors, noise 1e-5, eps 1e-4, FP32, split-bf16"}
 
 
+def algorithmic_bytes(dims, ranks, order, elem):
+    """Bytes an ST-HOSVD must move at least: per mode, the Gram reads Y_n and
+    the TTM reads Y_n and writes Y_{n+1}."""
+    cur = list(dims)
+    total = 0
+    for n in order:
+        ny = math.prod(cur)
+        cur[n] = ranks[n]
+        total += (2 * ny + math.prod(cur)) * elem
+    return total
+
+
+def combustion256_leg(dev, steps, warmup):
+    """The largest single-GPU workload (256x256x256x64x16 stored FP32, 68.7 GB)
+    on the mixed path in mode order 1..5 and 5..1 (Sec. VII: the order sets
+    how much data the later modes move)."""
+    w = synth.WORKLOADS["combustion256"]
+    log(f"[combustion256] generating {w.dims} FP32")
+    x = w.make(dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    in_bytes = x.numel() * x.element_size()
+    res = {}
+    for name, order in (("order_1..5", tuple(range(5))), ("order_5..1", (4, 3, 2, 1, 0))):
+        comp = tucker.Compressor(w.dims, x.dtype, dev, w.eps, order=order,
+                                 gram_precision="split_bf16", ttm_precision="bf16x3")
+        for _ in range(warmup):
+            comp.run(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            comp.run(x)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        r = comp.result(copy=True)
+        del comp
+        torch.cuda.empty_cache()
+        alg = algorithmic_bytes(w.dims, r.ranks, order, x.element_size())
+        res[name] = {"ms": round(ms, 3), "input_gbs": round(in_bytes / (ms / 1e3) / 1e9, 1),
+                     "algorithmic_bytes": alg,
+                     "algorithmic_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+                     "ranks": list(r.ranks), "fp64_modes": list(r.fp64_modes),
+                     "relerr_estimate": math.sqrt(sum(r.discarded) / r.norm2)}
+        log(f"[combustion256] {name}: {ms:.2f} ms, {res[name]['input_gbs']} GB/s input, "
+            f"{alg / 1e9:.1f} GB algorithmic ({res[name]['algorithmic_gbs']} GB/s), "
+            f"ranks {r.ranks}")
+        del r
+    del x
+    torch.cuda.empty_cache()
+    res["workload"] = ("combustion256: 256x256x256x64x16 planted Tucker, ranks (32,32,32,16,8), "
+                       "decay 0.8, cosine factors, noise 1e-5, eps 1e-4, stored FP32, mixed path")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +311,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-c256", action="store_true",
+                    help="skip the 68.7 GB combustion256 leg (mode orders 1..5 and 5..1)")
     ap.add_argument("--gram-reps", type=int, default=10)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="counter runs: only the mode-1 split Gram and TTM of the FP32 tensor "
@@ -343,6 +401,10 @@ def main():
         x = x64 = x32 = None
         torch.cuda.empty_cache()
         out["batch64"] = batch_leg(dev, args.steps, args.warmup, tune=not args.no_autotune)
+    if not args.no_c256:
+        x = x64 = x32 = None
+        torch.cuda.empty_cache()
+        out["combustion256"] = combustion256_leg(dev, max(1, args.steps // 2), 1)
     print(json.dumps(out), flush=True)
 
 

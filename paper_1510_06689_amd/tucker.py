@@ -324,7 +324,15 @@ class Compressor:
                                           _aligned(self.ws), self.ws_bytes,
                                           _stream(self.device)))
 
-    def result(self) -> TuckerTensor:
+    def result(self, copy: bool = False) -> TuckerTensor:
+        """The last run's outputs: views into this compressor's buffers (valid
+        until its next run, and keeping those buffers alive), or with ``copy``
+        compact copies that hold only the ``prod R_n`` core elements."""
+        if copy:
+            r = self.result()
+            return TuckerTensor(_fortran_copy(r.core), [_fortran_copy(f) for f in r.factors],
+                                r.ranks, [e.clone() for e in r.eigvals], r.discarded, r.norm2,
+                                r.fp64_modes, r.ttm_precision)
         n = len(self.dims)
         ranks = tuple(int(self.out.ranks[k]) for k in range(n))
         core = self.core_buf[:math.prod(ranks)].view(tuple(reversed(ranks))).permute(
@@ -348,10 +356,7 @@ def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
     c = Compressor(x.shape, x.dtype, x.device, eps, order, ranks, max_ranks, gram_precision,
                    ttm_precision)
     c.run(x)
-    r = c.result()
-    return TuckerTensor(_fortran_copy(r.core), [_fortran_copy(f) for f in r.factors], r.ranks,
-                        [e.clone() for e in r.eigvals], r.discarded, r.norm2, r.fp64_modes,
-                        r.ttm_precision)
+    return c.result(copy=True)
 
 
 def _fortran_copy(t: torch.Tensor) -> torch.Tensor:

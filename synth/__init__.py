@@ -20,7 +20,8 @@ Recipe (used for every workload):
 
 Tensors are returned with logical shape ``(I_1, ..., I_N)`` and mode 1
 fastest in memory (Fortran strides), the layout of the paper's local
-tensors.
+tensors.  Tensors above 32 GB in FP64 are built one slab of the last mode at
+a time (same recipe, the noise drawn slab after slab).
 """
 from __future__ import annotations
 
@@ -114,6 +115,8 @@ def planted_tucker(dims: Sequence[int], ranks: Sequence[int], *, rho: float = 1.
         shape = [1] * n
         shape[n - 1 - k] = ranks[k]
         core_c = core_c * scale.view(shape)
+    if math.prod(dims) * 8 > _SLAB_BYTES and not return_parts:
+        return _planted_by_slabs(dims, ranks, factors, core_c, noise, noise_mode, g, dtype, dev)
     # X0 = G x_1 U_1 ... x_N U_N; mode k is axis n-1-k of the C-order array.
     t = core_c
     for k in sorted(range(n), key=lambda m: dims[m] / ranks[m]):
@@ -145,6 +148,38 @@ def planted_tucker(dims: Sequence[int], ranks: Sequence[int], *, rho: float = 1.
     if return_parts:
         core = _to_fortran(core_c)
         return out, core, factors
+    return out
+
+
+# Tensors whose FP64 form exceeds this are built one last-mode slab at a time.
+_SLAB_BYTES = 1 << 35
+
+
+def _planted_by_slabs(dims, ranks, factors, core_c, noise, noise_mode, g, dtype, dev):
+    """``planted_tucker`` for tensors too large to hold in FP64 (with its
+    temporaries): slab t of the last mode is ``(G x_N U_N[t, :]) x_1 U_1 ...
+    x_{N-1} U_{N-1}``, formed in FP64, given its noise, rounded once to
+    ``dtype`` and stored; the noise comes from the same generator, slab after
+    slab.  Only ``noise_mode="sigma"`` applies (``"exact"`` needs the whole
+    tensor's norm first)."""
+    if noise > 0 and noise_mode != "sigma":
+        raise ValueError("slab-wise generation supports noise_mode='sigma' only")
+    n = len(dims)
+    out = fortran_empty(dims, dtype, dev)
+    out_c = out.permute(*reversed(range(n)))          # C order (I_N, ..., I_1), contiguous
+    sigma = noise * torch.linalg.vector_norm(core_c).item() / math.sqrt(math.prod(dims))
+    order = sorted(range(n - 1), key=lambda m: dims[m] / ranks[m])
+    for t in range(dims[n - 1]):
+        s = torch.tensordot(factors[n - 1][t], core_c, dims=([0], [0]))  # (R_{N-1}, ..., R_1)
+        for k in order:
+            ax = n - 2 - k
+            s = torch.tensordot(s, factors[k], dims=([ax], [1]))
+            s = torch.movedim(s, -1, ax).contiguous()
+        if noise > 0:
+            s.add_(torch.randn(s.shape, generator=g, dtype=torch.float64, device=dev),
+                   alpha=sigma)
+        out_c[t].copy_(s)
+        del s
     return out
 
 

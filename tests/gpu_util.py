@@ -40,3 +40,23 @@ def ttm_tolerance(y, n, v, u=U64):
     import oracle
     jn = y.shape[n]
     return (jn + 2) * u * oracle.ttm(np.abs(y), n, np.abs(v)) + 1e-300
+
+
+def mode1_rows(x, i, j):
+    """Rows i and j of the mode-1 unfolding of a device tensor, as a
+    2 x I_2 x .. x I_N host array (FP64)."""
+    out = np.empty((2,) + tuple(x.shape[1:]), order="F")
+    out[0] = x[i].double().cpu().numpy()
+    out[1] = x[j].double().cpu().numpy()
+    return out
+
+
+def split_gram_bound(sub):
+    """Elementwise bound of the split-bf16 Gram (mode 1) of a row slice:
+    2^-16 (m_i |x_j|_1 + m_j |x_i|_1) + 2^-24 K m_i m_j."""
+    import oracle
+    m = oracle.unfold(sub, 0)
+    rmax = np.abs(m).max(axis=1)
+    l1 = np.abs(m).sum(axis=1)
+    k = m.shape[1]
+    return 2.0**-16 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-24 * k * np.outer(rmax, rmax)

@@ -18,7 +18,7 @@ import torch
 import oracle
 import synth
 from paper_1510_06689_amd import tucker
-from gpu_util import U32, U64, say
+from gpu_util import U32, U64, mode1_rows, say, split_gram_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -39,23 +39,6 @@ def tensors():
     torch.cuda.empty_cache()
 
 
-def _rows(x, i, j):
-    """Rows i and j of the mode-1 unfolding as a 2 x I2 x .. x I5 host tensor."""
-    out = np.empty((2,) + tuple(x.shape[1:]), order="F")
-    out[0] = x[i].double().cpu().numpy()
-    out[1] = x[j].double().cpu().numpy()
-    return out
-
-
-def _split_bound(sub):
-    """Elementwise bound of the split-bf16 Gram for a two-row slice."""
-    m = oracle.unfold(sub, 0)
-    rmax = np.abs(m).max(axis=1)
-    l1 = np.abs(m).sum(axis=1)
-    k = m.shape[1]
-    return 2.0**-16 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-24 * k * np.outer(rmax, rmax)
-
-
 @pytest.mark.parametrize("path", ["fp64", "mixed"])
 def test_fullsize_mode1_gram_entries(tensors, path):
     x = tensors[0] if path == "fp64" else tensors[1]
@@ -65,12 +48,12 @@ def test_fullsize_mode1_gram_entries(tensors, path):
     s = s.cpu().numpy()
     k = x.numel() // x.shape[0]
     for i, j in PAIRS:
-        sub = _rows(x, i, j)
+        sub = mode1_rows(x, i, j)
         ref = oracle.gram(sub, 0)                       # [[S_ii, S_ij], [S_ji, S_jj]]
         d = np.sqrt(np.diag(ref))
         tol = (k + 2) * U64 * np.outer(d, d)
         if path == "mixed":
-            tol = tol + _split_bound(sub)
+            tol = tol + split_gram_bound(sub)
         got = np.array([[s[i, i], s[i, j]], [s[j, i], s[j, j]]])
         say(f"{path} S[{i},{j}] = {got[0, 1]:.12e} oracle {ref[0, 1]:.12e}")
         assert np.all(np.abs(got - ref) <= tol), (i, j, got - ref, tol)
