@@ -138,17 +138,20 @@ __device__ __forceinline__ void gram_f64_body(const T* __restrict__ y, const Til
     }
 }
 
+// P tile ranges x G pair groups, one workgroup each (xcd_range_group).
 template <typename T, int JB, int KT, int NPW, int KS>
 __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
-    const T* __restrict__ y, TileMap tm, int nb, int npairs, int pairs_per_group,
+    const T* __restrict__ y, TileMap tm, int nb, int npairs, int pairs_per_group, int P, int G,
     double* __restrict__ partial) {
     extern __shared__ double lds[];
-    const int g0 = blockIdx.y * pairs_per_group;
+    int p, g;
+    xcd_range_group(blockIdx.x, G, p, g);
+    const int g0 = g * pairs_per_group;
     const int npg = min(npairs - g0, pairs_per_group);
-    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
-    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    const int64_t t0 = tm.ntiles * (int64_t)p / P;
+    const int64_t t1 = tm.ntiles * (int64_t)(p + 1) / P;
     gram_f64_body<T, JB, KT, NPW, KS>(y, tm, nb, g0, npg, t0, t1,
-                                      partial + (int64_t)blockIdx.x * npairs * 256, lds);
+                                      partial + (int64_t)p * npairs * 256, lds);
 }
 
 // S[r + J c] for the upper block pairs.  Each workgroup reduces 64 outputs;
@@ -237,10 +240,8 @@ GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
     pl.G = (pl.npairs + gs.per_group - 1) / gs.per_group;
     pl.pairs_per_group = (pl.npairs + pl.G - 1) / pl.G;
     TileMap tm = make_tiles(v, pl.KT);
-    int64_t want = (int64_t)2 * device_cu_count() / pl.G;
-    if (want < 1) want = 1;
-    pl.P = (int)(tm.ntiles < want ? tm.ntiles : want);
-    if (pl.P < 1) pl.P = 1;
+    const int64_t want = xcd_round_want((int64_t)2 * device_cu_count() / pl.G, pl.G);
+    pl.P = xcd_ranges(tm.ntiles, want, pl.G);
     pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
     pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
     return pl;
@@ -254,8 +255,8 @@ static int launch_partial(const T* y, const TileMap& tm, const GramPlan& pl, dou
     auto fn = gram_partial_f64<T, JB, gs.KT, gs.NPW, gs.KS>;
     TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-    hipLaunchKernelGGL(fn, dim3(pl.P, pl.G), dim3(kGramThreads), lds, st, y, tm, pl.nb, pl.npairs,
-                       pl.pairs_per_group, partial);
+    hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kGramThreads), lds, st, y, tm, pl.nb,
+                       pl.npairs, pl.pairs_per_group, pl.P, pl.G, partial);
     TK_HIP(hipGetLastError());
     return TK_OK;
 }

@@ -345,16 +345,18 @@ __device__ __forceinline__ void gram_bf16s_body(
     }
 }
 
+// P tile ranges x G pair groups, one workgroup each (xcd_range_group).
 template <int JB, int KT, int NPW, int MODE>
 __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
     const float* __restrict__ y, TileMap tm, int npairs32, int pairs_per_group, int npairs16,
-    double* __restrict__ partial) {
+    int P, int G, double* __restrict__ partial) {
     extern __shared__ double lds_raw[];
-    const int64_t t0 = tm.ntiles * (int64_t)blockIdx.x / gridDim.x;
-    const int64_t t1 = tm.ntiles * (int64_t)(blockIdx.x + 1) / gridDim.x;
-    gram_bf16s_body<JB, KT, NPW, MODE>(y, tm, npairs32, pairs_per_group, npairs16, blockIdx.y,
-                                      t0, t1, partial + (int64_t)blockIdx.x * npairs16 * 256,
-                                      lds_raw);
+    int p, g;
+    xcd_range_group(blockIdx.x, G, p, g);
+    const int64_t t0 = tm.ntiles * (int64_t)p / P;
+    const int64_t t1 = tm.ntiles * (int64_t)(p + 1) / P;
+    gram_bf16s_body<JB, KT, NPW, MODE>(y, tm, npairs32, pairs_per_group, npairs16, g, t0, t1,
+                                      partial + (int64_t)p * npairs16 * 256, lds_raw);
 }
 
 // Static schedule per padded extent: tile width, pairs per wave, pair groups
@@ -392,10 +394,8 @@ static GramPlan mx_plan(const ModeView& v) {
     pl.pairs_per_group = (npairs32 + gs.G - 1) / gs.G;
     pl.nb = 2 * nb32;  // 16-blocks, for the shared reduction
     pl.npairs = pl.nb * (pl.nb + 1) / 2;
-    int64_t want = (int64_t)gs.per_cu * device_cu_count() / pl.G;
-    if (want < 1) want = 1;
-    pl.P = (int)(tm.ntiles < want ? tm.ntiles : want);
-    if (pl.P < 1) pl.P = 1;
+    const int64_t want = xcd_round_want((int64_t)gs.per_cu * device_cu_count() / pl.G, pl.G);
+    pl.P = xcd_ranges(tm.ntiles, want, pl.G);
     pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
     pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
     return pl;
@@ -420,8 +420,8 @@ static int mx_launch(const float* y, const TileMap& tm, const GramPlan& pl, doub
     TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     const int nb32 = JB / 32;
-    hipLaunchKernelGGL(fn, dim3(pl.P, pl.G), dim3(kMxThreads), lds, st, y, tm,
-                       nb32 * (nb32 + 1) / 2, pl.pairs_per_group, pl.npairs, partial);
+    hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kMxThreads), lds, st, y, tm,
+                       nb32 * (nb32 + 1) / 2, pl.pairs_per_group, pl.npairs, pl.P, pl.G, partial);
     TK_HIP(hipGetLastError());
     return TK_OK;
 }

@@ -223,6 +223,40 @@ __host__ __device__ inline ModeView batch_mode_view(const BatchView& b) {
     return v;
 }
 
+// MI355X has 8 XCDs, each with its own L2, and deals consecutive workgroup
+// ids to them round-robin.  A Gram whose block pairs are split into G > 1
+// groups reads every tile range G times; placing the G workgroups of one
+// range on one XCD in consecutive slots lets them stream the same tiles
+// through that XCD's L2.  The launch has P * G workgroups, P a multiple of
+// kXcds (any mapping would be correct; this one is about locality).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void xcd_range_group(int b, int G, int& p, int& g) {
+    if (G == 1) {
+        p = b;
+        g = 0;
+        return;
+    }
+    const int x = b % kXcds, s = b / kXcds;
+    g = s % G;
+    p = x + kXcds * (s / G);
+}
+
+// Tile ranges for a G-group Gram: min(ntiles, want), and for G > 1 a multiple
+// of kXcds (ranges beyond the tiles are empty and write zero partials).
+// `want` is rounded the same way by the caller's workspace bound.
+inline int64_t xcd_round_want(int64_t want, int G) {
+    if (G == 1) return want < 1 ? 1 : want;
+    want = want / kXcds * kXcds;
+    return want < kXcds ? kXcds : want;
+}
+inline int xcd_ranges(int64_t ntiles, int64_t want, int G) {
+    int64_t p = ntiles < want ? ntiles : want;
+    if (p < 1) p = 1;
+    if (G > 1) p = (p + kXcds - 1) / kXcds * kXcds;  // <= want: want is a multiple of kXcds
+    return (int)p;
+}
+
 // Task of workgroup `wg` in a launch whose tasks (stride bytes apart, each
 // starting with a BatchView) own consecutive workgroup ranges.
 __device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, int ntasks,

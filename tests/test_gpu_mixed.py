@@ -58,6 +58,9 @@ GRAM_CASES = [
     ((24, 256, 3), (1,)),
     ((47, 23, 32, 16), (2, 3)),
     ((47, 23, 1, 16), (3,)),
+    ((100, 9, 13), (0,)),       # J % 4 == 0 with L == 1: 16-byte column pieces, J class 128
+    ((132, 5, 7), (0,)),        # the same for J class 256 (three pair groups)
+    ((128, 1000), (0,)),        # several tiles per workgroup and a ragged last tile
 ]
 
 
