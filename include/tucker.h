@@ -83,7 +83,10 @@ typedef enum tk_gram_precision {
      * its row's maximum.  In sthosvd_compress a rank found from such a Gram
      * is accepted only when the eps threshold lies clear of the tail sums on
      * both sides by a margin of 2^-27 trace R (J - R) / J^2; otherwise that
-     * mode's Gram is recomputed in FP64 (tk_tucker.fp64_modes). */
+     * mode's Gram is recomputed in FP64 (tk_tucker.fp64_modes).  There, modes
+     * with J <= 32 whose unfolding has at most 2^26 elements take the FP64
+     * Gram directly: at J <= 32 it costs no more on FP32 data (arithmetic
+     * intensity below the FP64 matrix-core ridge) and needs no guard. */
     TK_GRAM_SPLIT_BF16 = 1
 } tk_gram_precision;
 

@@ -64,6 +64,41 @@ static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 using namespace tk;
 
+// Scalar block of one compression (device): [0] ||X||^2, [1..8] discarded
+// sums, [16..23] ranks, [32] status flags.  The per-mode readback copies
+// its first 33 doubles in one transfer into pinned host memory allocated
+// once per thread (kept for the thread's lifetime: 512 bytes); pageable
+// stack memory is the fallback if that allocation fails.
+static double* pinned_scalars() {
+    static thread_local double* p = nullptr;
+    static thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void**)&p, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    return p;
+}
+
+static int read_scalars(const double* scal_dev, hipStream_t st, int n, int64_t* rank, double* nu,
+                        int* flags) {
+    double local[33];
+    double* h = pinned_scalars();
+    if (!h) h = local;
+    TK_HIP(hipMemcpyAsync(h, scal_dev, 33 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TK_HIP(hipStreamSynchronize(st));
+    int64_t r;
+    int f;
+    memcpy(&r, h + 16 + n, sizeof r);
+    memcpy(&f, h + 32, sizeof f);
+    *rank = r;
+    *nu = h[0];
+    *flags = f;
+    return TK_OK;
+}
+
 extern "C" {
 
 const char* tk_status_string(int status) {
@@ -317,8 +352,16 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     for (int s = 0; s < N; ++s) {
         const int n = pl.order[s];
         ModeView v = mode_view(cur, N, n);
-        TK_TRY(launch_gram(ycur, x->dtype, v, opt->gram_precision, S, s == 0 ? nu_dev : nullptr,
-                           gram_ws, pl.gram_bytes, st));
+        // A narrow mode (J <= 32) over a small unfolding takes the FP64 Gram
+        // even on the mixed path: at J <= 32 its arithmetic intensity on FP32
+        // data, (J + 1) / 4 flop/B, is below the FP64 MFMA ridge, so it costs
+        // no more than the split one, and it needs no guard recomputation.
+        int gprec = opt->gram_precision;
+        if (gprec == TK_GRAM_SPLIT_BF16 && v.J <= 32 &&
+            (double)v.L * (double)v.J * (double)v.B <= kSmallFp64GramElems)
+            gprec = TK_GRAM_FP64;
+        TK_TRY(launch_gram(ycur, x->dtype, v, gprec, S, s == 0 ? nu_dev : nullptr, gram_ws,
+                           pl.gram_bytes, st));
         EigArgs ea;
         ea.s = S;
         ea.J = v.J;
@@ -332,7 +375,7 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         ea.disc_out = disc_dev + n;
         ea.flags = flags_dev;
         ea.scratch = eig_ws;
-        const bool mixed = opt->gram_precision != TK_GRAM_FP64;
+        const bool mixed = gprec != TK_GRAM_FP64;
         ea.guard = (mixed && !opt->fixed_ranks) ? kSplitGramGuard : 0.0;
         TK_TRY(launch_eig(ea, st));
 
@@ -340,14 +383,12 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         if (opt->fixed_ranks && s > 0) {
             R = opt->fixed_ranks[n];
         } else {
-            // the rank (and, after the first Gram, ||X||^2) must reach the host
-            double hbuf[2];
+            // the rank (and, after the first Gram, ||X||^2) must reach the host:
+            // one copy of the scalar block into pinned memory, then a sync
             int64_t rk;
             int flags;
-            TK_HIP(hipMemcpyAsync(&rk, rank_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-            TK_HIP(hipMemcpyAsync(hbuf, nu_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-            TK_HIP(hipMemcpyAsync(&flags, flags_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-            TK_HIP(hipStreamSynchronize(st));
+            double nu_read;
+            TK_TRY(read_scalars(scal, st, n, &rk, &nu_read, &flags));
             if (flags & 4) {
                 // the mixed Gram cannot certify this rank: redo the mode in FP64
                 TK_HIP(hipMemsetAsync(flags_dev, 0, sizeof(int), st));
@@ -355,14 +396,10 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
                                    gram_ws, pl.gram_bytes, st));
                 ea.guard = 0.0;
                 TK_TRY(launch_eig(ea, st));
-                TK_HIP(hipMemcpyAsync(&rk, rank_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost,
-                                      st));
-                TK_HIP(hipMemcpyAsync(hbuf, nu_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-                TK_HIP(hipMemcpyAsync(&flags, flags_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-                TK_HIP(hipStreamSynchronize(st));
+                TK_TRY(read_scalars(scal, st, n, &rk, &nu_read, &flags));
                 fp64_modes |= 1u << n;
             }
-            nu_host = hbuf[0];
+            nu_host = nu_read;
             if (!std::isfinite(nu_host))
                 return fail(TK_ERR_NONFINITE, "sthosvd_compress: input holds Inf or NaN");
             if (flags & 2)

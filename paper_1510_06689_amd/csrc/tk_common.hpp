@@ -189,6 +189,9 @@ constexpr double kSplitGramGuard = 8.0 / 1073741824.0;
 // which adds about 2^-34 ||X||^2 to later modes' tail sums; below
 // eps^2 / N = 8 * 2^-34 the threshold would feel it, so the TTMs run in FP64.
 constexpr double kSplitTtmFloor = 8.0 / 17179869184.0;
+// Mixed path: modes with J <= 32 and at most this many unfolding elements
+// use the FP64 Gram (2^26: 256 MB of FP32).
+constexpr double kSmallFp64GramElems = 67108864.0;
 size_t eig_scratch_doubles(int J);
 int launch_eig(const EigArgs& a, hipStream_t st);
 size_t eig_lds_bytes(int J);

@@ -119,7 +119,11 @@ def test_batch_guard_recomputes_on_device():
             f"fp64 modes batch {r.fp64_modes} single {single.fp64_modes}")
         assert r.ranks == ref.ranks == ws[i].ranks
         rel, rel1 = _relerr(d, r), _relerr(d, single)
-        assert rel <= eps and abs(rel - rel1) <= 1e-2 * rel1
+        # the two paths may take a mode's Gram in different precisions (the
+        # single path uses FP64 for narrow small modes): an accepted split
+        # rank keeps the discarded energy within the guard margin,
+        # 8 2^-30 tr R (J - R) / J^2 <= 2^-29 ||X||^2, per mode
+        assert rel <= eps and abs(rel**2 - rel1**2) <= len(x.shape) * 2.0**-29
 
 
 def test_batch_rejects_unsupported():
