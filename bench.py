@@ -18,6 +18,7 @@ timed on a bounded slab of the same tensor.
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import math
 import os
@@ -301,6 +302,76 @@ def combustion256_leg(dev, steps, warmup):
     return res
 
 
+def paper_flops(dims, ranks, order):
+    """Flops by the paper's counts: Gram 2 I_n #Y_n, TTM 2 R_n #Y_n per mode."""
+    cur, total = list(dims), 0
+    for n in order:
+        ny = math.prod(cur)
+        total += 2 * (dims[n] + ranks[n]) * ny
+        cur[n] = ranks[n]
+    return total
+
+
+def time_fixed(x, dims, ranks, order, steps, warmup, gp="fp64", tp="fp64"):
+    comp = tucker.Compressor(dims, x.dtype, x.device, 0.0, order=order, ranks=ranks,
+                             gram_precision=gp, ttm_precision=tp)
+    for _ in range(warmup):
+        comp.run(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        comp.run(x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    got = comp.result().ranks
+    del comp
+    return ms, got
+
+
+def paper_shapes_leg(dev, steps, warmup):
+    """The paper's own workload shapes on this path (FP64, fixed ranks):
+    200^4 -> 20^4 (Sec. VII strong-scaling problem; one node there: ~3 s)
+    and the 25x250x250x250 -> 10x10x100x100 mode-order experiment over all
+    24 orders, with the orders the two greedy heuristics of Sec. VII pick
+    and the least-traffic order."""
+    out = {}
+    dims, ranks = (200, 200, 200, 200), (20, 20, 20, 20)
+    x = synth.planted_tucker(dims, ranks, rho=1.0, factor_kind="gaussian", noise=1e-6,
+                             noise_mode="sigma", seed=11, device=dev)
+    torch.cuda.synchronize()
+    ms, got = time_fixed(x, dims, ranks, tuple(range(4)), steps, warmup)
+    fl = paper_flops(dims, ranks, range(4))
+    out["200^4->20^4"] = {"ms": round(ms, 3), "gflops_paper_count": round(fl / ms / 1e6, 1),
+                          "frac_fp64_peak": round(fl / ms / 1e9 / FP64_MFMA_PEAK_TFS, 4),
+                          "input_gbs": round(x.numel() * 8 / ms / 1e6, 1), "ranks": list(got),
+                          "paper_one_node_s": 3.0}
+    log(f"[paper] 200^4 -> 20^4 FP64: {ms:.2f} ms, {fl / ms / 1e6:.0f} GFLOP/s (paper's counts)")
+    del x
+    torch.cuda.empty_cache()
+    dims, ranks = (25, 250, 250, 250), (10, 10, 100, 100)
+    x = synth.planted_tucker(dims, ranks, rho=1.0, factor_kind="gaussian", noise=1e-6,
+                             noise_mode="sigma", seed=12, device=dev)
+    torch.cuda.synchronize()
+    times = {}
+    for order in itertools.permutations(range(4)):
+        ms, _ = time_fixed(x, dims, ranks, order, steps, warmup)
+        times[order] = ms
+    best = min(times, key=times.get)
+    worst = max(times, key=times.get)
+    picks = {rule: tucker.mode_order(dims, ranks, rule, 8) for rule in ("flops", "ratio", "bytes")}
+    out["25x250x250x250->10x10x100x100"] = {
+        "ms_by_order": {"".join(str(k + 1) for k in o): round(t, 3) for o, t in times.items()},
+        "best_order": "".join(str(k + 1) for k in best), "best_ms": round(times[best], 3),
+        "worst_order": "".join(str(k + 1) for k in worst), "worst_ms": round(times[worst], 3),
+        "heuristics": {rule: {"order": "".join(str(k + 1) for k in o), "ms": round(times[o], 3)}
+                       for rule, o in picks.items()}}
+    log(f"[paper] mode-order sweep: best {best} {times[best]:.2f} ms, worst {worst} "
+        f"{times[worst]:.2f} ms; " + ", ".join(f"{r} {o} {times[o]:.2f} ms" for r, o in picks.items()))
+    del x
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +382,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the paper's 200^4 workload and its mode-order sweep")
     ap.add_argument("--no-c256", action="store_true",
                     help="skip the 68.7 GB combustion256 leg (mode orders 1..5 and 5..1)")
     ap.add_argument("--gram-reps", type=int, default=10)
@@ -401,6 +474,10 @@ def main():
         x = x64 = x32 = None
         torch.cuda.empty_cache()
         out["batch64"] = batch_leg(dev, args.steps, args.warmup, tune=not args.no_autotune)
+    if not args.no_paper_shapes:
+        x = x64 = x32 = None
+        torch.cuda.empty_cache()
+        out["paper_shapes"] = paper_shapes_leg(dev, max(1, args.steps // 2), 1)
     if not args.no_c256:
         x = x64 = x32 = None
         torch.cuda.empty_cache()

@@ -192,6 +192,34 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
                      tk_tucker* out, void* ws, size_t ws_bytes, void* stream);
 size_t sthosvd_workspace_bytes(const tk_shape* x, const tk_options* opt);
 
+/* ------------------------------------------------------------ mode order
+ * Alg. 1 processes the modes in any order; the order changes the work of
+ * the later modes (Sec. VII, mode-order experiment).  Given the extents
+ * and the (expected or fixed) ranks, this host-only call writes an order to
+ * order_out[0..ndim-1]:
+ *   TK_ORDER_GREEDY_FLOPS  at each step the remaining mode with the fewest
+ *                          flops in that step (Gram 2 I_n #Y plus TTM
+ *                          2 R_n #Y, so the least I_n + R_n): the
+ *                          heuristic of the ST-HOSVD authors cited there;
+ *   TK_ORDER_GREEDY_RATIO  at each step the remaining mode with the largest
+ *                          compression ratio I_n / R_n (the alternative
+ *                          heuristic given there);
+ *   TK_ORDER_MIN_BYTES     the order that minimises this library's
+ *                          algorithmic HBM traffic, sum over steps of
+ *                          (2 #Y_n + #Y_{n+1}) elem_bytes (every Gram reads
+ *                          Y_n, every TTM reads Y_n and writes Y_{n+1}),
+ *                          by exhaustive search (ndim <= 8).
+ * Ties go to the lowest mode index (lexicographically first order).
+ * Returns TK_OK, or TK_ERR_INVALID_ARG for ndim outside [1, 8], a NULL
+ * pointer, an extent < 1, a rank outside [1, extent] or an unknown rule. */
+typedef enum tk_order_rule {
+    TK_ORDER_GREEDY_FLOPS = 0,
+    TK_ORDER_GREEDY_RATIO = 1,
+    TK_ORDER_MIN_BYTES = 2
+} tk_order_rule;
+int sthosvd_mode_order(int ndim, const int64_t* dims, const int64_t* ranks, int rule,
+                       int elem_bytes, int* order_out);
+
 /* ---------------------------------------------------------- reconstruction */
 
 /*

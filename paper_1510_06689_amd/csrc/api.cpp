@@ -1,6 +1,7 @@
 // C-ABI entry points: host-side validation (no HIP call before it), workspace
 // planning, and the mode loop of Alg. 1 (ST-HOSVD) and of the Tucker
 // reconstruction (Sec. II-C).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -566,6 +567,65 @@ int tucker_error_metrics(const tk_shape* x, const void* x_dev, const void* xhat_
     TK_TRY(launch_error_metrics(x_dev, xhat_dev, x->dtype, n, part, nb, out3, st));
     TK_HIP(hipMemcpyAsync(out_host, out3, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     TK_HIP(hipStreamSynchronize(st));
+    return TK_OK;
+}
+
+int sthosvd_mode_order(int ndim, const int64_t* dims, const int64_t* ranks, int rule,
+                       int elem_bytes, int* order_out) {
+    if (ndim < 1 || ndim > TK_MAX_NDIM)
+        return fail(TK_ERR_INVALID_ARG, "sthosvd_mode_order: ndim %d outside [1, %d]", ndim,
+                    TK_MAX_NDIM);
+    if (!dims || !ranks || !order_out)
+        return fail(TK_ERR_INVALID_ARG, "sthosvd_mode_order: NULL pointer");
+    for (int k = 0; k < ndim; ++k)
+        if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > dims[k])
+            return fail(TK_ERR_INVALID_ARG, "sthosvd_mode_order: mode %d has extent %lld, rank %lld",
+                        k, (long long)dims[k], (long long)ranks[k]);
+    if (rule == TK_ORDER_GREEDY_FLOPS || rule == TK_ORDER_GREEDY_RATIO) {
+        bool used[TK_MAX_NDIM] = {false};
+        for (int s = 0; s < ndim; ++s) {
+            int best = -1;
+            for (int k = 0; k < ndim; ++k) {
+                if (used[k]) continue;
+                if (best < 0) {
+                    best = k;
+                    continue;
+                }
+                bool better;
+                if (rule == TK_ORDER_GREEDY_FLOPS)  // least I + R (#Y is common to all choices)
+                    better = dims[k] + ranks[k] < dims[best] + ranks[best];
+                else  // largest I / R, compared exactly as I_k R_best > I_best R_k
+                    better = (double)dims[k] * (double)ranks[best] >
+                             (double)dims[best] * (double)ranks[k];
+                if (better) best = k;
+            }
+            used[best] = true;
+            order_out[s] = best;
+        }
+        return TK_OK;
+    }
+    if (rule != TK_ORDER_MIN_BYTES)
+        return fail(TK_ERR_INVALID_ARG, "sthosvd_mode_order: unknown rule %d", rule);
+    if (elem_bytes < 1) return fail(TK_ERR_INVALID_ARG, "sthosvd_mode_order: elem_bytes < 1");
+    int perm[TK_MAX_NDIM];
+    for (int k = 0; k < ndim; ++k) perm[k] = k;
+    double best_cost = -1.0;
+    do {  // permutations in lexicographic order: the first minimum wins ties
+        double cur[TK_MAX_NDIM], cost = 0.0;
+        for (int k = 0; k < ndim; ++k) cur[k] = (double)dims[k];
+        for (int s = 0; s < ndim; ++s) {
+            double ny = 1.0;
+            for (int k = 0; k < ndim; ++k) ny *= cur[k];
+            const int n = perm[s];
+            cur[n] = (double)ranks[n];
+            cost += 2.0 * ny + ny / (double)dims[n] * (double)ranks[n];
+        }
+        cost *= (double)elem_bytes;
+        if (best_cost < 0.0 || cost < best_cost) {
+            best_cost = cost;
+            for (int k = 0; k < ndim; ++k) order_out[k] = perm[k];
+        }
+    } while (std::next_permutation(perm, perm + ndim));
     return TK_OK;
 }
 

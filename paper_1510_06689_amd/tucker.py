@@ -38,8 +38,8 @@ EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "ttm_mode_n", "sthosvd_compres
            "sthosvd_workspace_bytes", "tucker_reconstruct", "reconstruct_workspace_bytes",
            "tucker_error_metrics", "error_metrics_workspace_bytes",
            "sthosvd_batch_workspace_bytes", "sthosvd_batch_create", "sthosvd_batch_run",
-           "sthosvd_batch_finish", "sthosvd_batch_destroy", "tk_status_string",
-           "tk_last_error")
+           "sthosvd_batch_finish", "sthosvd_batch_destroy", "sthosvd_mode_order",
+           "tk_status_string", "tk_last_error")
 
 
 class TuckerError(RuntimeError):
@@ -117,6 +117,9 @@ def library() -> ctypes.CDLL:
         "sthosvd_batch_run": (_int, [_vp, _vp]),
         "sthosvd_batch_finish": (_int, [_vp, _vp]),
         "sthosvd_batch_destroy": (None, [_vp]),
+        "sthosvd_mode_order": (_int, [_int, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), _int, _int,
+                                      ctypes.POINTER(ctypes.c_int)]),
         "tk_status_string": (ctypes.c_char_p, [_int]),
         "tk_last_error": (ctypes.c_char_p, []),
     }
@@ -407,6 +410,23 @@ def error_metrics(x: torch.Tensor, xhat: torch.Tensor):
     _check(lib.tucker_error_metrics(ctypes.byref(sh), x.data_ptr(), xhat.data_ptr(), out,
                                     _aligned(ws), need, _stream(x.device)))
     return float(out[0]), float(out[1]), float(out[2])
+
+
+ORDER_RULES = {"flops": 0, "ratio": 1, "bytes": 2}
+
+
+def mode_order(dims, ranks, rule: str = "bytes", elem_bytes: int = 4) -> tuple:
+    """A mode order for Alg. 1 from the extents and (expected) ranks: the
+    greedy least-flops heuristic (``"flops"``), the greedy largest I_n/R_n
+    heuristic (``"ratio"``), both named in Sec. VII's mode-order
+    experiment, or the order with the least algorithmic HBM traffic of this
+    library (``"bytes"``, exhaustive).  Host-only; no GPU needed."""
+    n = len(dims)
+    d = (ctypes.c_int64 * n)(*[int(v) for v in dims])
+    r = (ctypes.c_int64 * n)(*[int(v) for v in ranks])
+    out = (ctypes.c_int * n)()
+    _check(library().sthosvd_mode_order(n, d, r, ORDER_RULES[rule], int(elem_bytes), out))
+    return tuple(int(v) for v in out)
 
 
 def compression_ratio(dims, ranks) -> float:
