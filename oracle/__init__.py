@@ -242,6 +242,51 @@ def sthosvd(x, eps: float, order=None, ranks=None) -> TuckerResult:
     return TuckerResult(g, factors, ranks_t, spectra, disc, float(nrm[0]), list(sw))
 
 
+@dataclass
+class HooiResult:
+    core: np.ndarray            # Fortran order, shape = ranks
+    factors: list               # U_n, I_n x R_n
+    ranks: tuple
+    fits: list                  # ||X||^2 - ||G||^2 after ST-HOSVD, then after each sweep
+    norm2: float                # ||X||^2
+    sweeps: int                 # sweeps run
+
+
+def hooi(x, eps: float, ranks=None, order=None, max_sweeps: int = 50,
+         tol: float = 0.0) -> HooiResult:
+    """Alg. 2 (HOOI) on the CPU in FP64.  Starts from ST-HOSVD (Alg. 1, with
+    ``eps`` or fixed ``ranks``); each sweep visits modes 1..N, forms
+    Y = X x_m U_m^T over every m != n (ascending m), takes the leading R_n
+    eigenvectors of Y_(n) Y_(n)^T as the new U_n, and after mode N forms the
+    core G = Y x_N U_N^T.  Stops when the fit ||X||^2 - ||G||^2 (the model
+    error, Sec. III) decreases by at most ``tol * ||X||^2`` in a sweep, or
+    after ``max_sweeps`` sweeps; ``tol < 0`` runs exactly ``max_sweeps``."""
+    x = _f64_fortran(x)
+    init = sthosvd(x, eps, order=order, ranks=ranks)
+    nd = x.ndim
+    rk = init.ranks
+    u = [f.copy() for f in init.factors]
+    nu = init.norm2
+    g = init.core
+    fits = [nu - float(np.sum(g * g))]
+    sweeps = 0
+    for _ in range(max_sweeps):
+        y = x
+        for n in range(nd):
+            y = x
+            for m in range(nd):
+                if m != n:
+                    y = ttm(y, m, u[m].T)
+            _, v, _ = sym_eig(gram(y, n))
+            u[n] = v[:, :rk[n]].copy()
+        g = ttm(y, nd - 1, u[nd - 1].T)
+        fits.append(nu - float(np.sum(g * g)))
+        sweeps += 1
+        if tol >= 0.0 and fits[-2] - fits[-1] <= tol * nu:
+            break
+    return HooiResult(g, u, rk, fits, nu, sweeps)
+
+
 def reconstruct(core, factors, full_dims=None) -> np.ndarray:
     """``X~ = G x_1 U_1 ... x_N U_N`` (Sec. II-C)."""
     core = _f64_fortran(core)
