@@ -312,6 +312,22 @@ def paper_flops(dims, ranks, order):
     return total
 
 
+def hooi_sweep_flops(dims, ranks):
+    """One HOOI sweep by the paper's counts: per mode n, the TTMs with every
+    U_m^T (m != n, ascending; 2 R_m #Y each) and the Gram (2 I_n #Y_n), then
+    the core TTM (2 R_N #Y)."""
+    total, nd = 0, len(dims)
+    for n in range(nd):
+        cur = list(dims)
+        for m in range(nd):
+            if m != n:
+                total += 2 * ranks[m] * math.prod(cur)
+                cur[m] = ranks[m]
+        total += 2 * dims[n] * math.prod(cur)
+    total += 2 * ranks[-1] * math.prod(list(ranks[:-1]) + [dims[-1]])
+    return total
+
+
 def time_fixed(x, dims, ranks, order, steps, warmup, gp="fp64", tp="fp64"):
     comp = tucker.Compressor(dims, x.dtype, x.device, 0.0, order=order, ranks=ranks,
                              gram_precision=gp, ttm_precision=tp)
@@ -346,7 +362,21 @@ def paper_shapes_leg(dev, steps, warmup):
                           "input_gbs": round(x.numel() * 8 / ms / 1e6, 1), "ranks": list(got),
                           "paper_one_node_s": 3.0}
     log(f"[paper] 200^4 -> 20^4 FP64: {ms:.2f} ms, {fl / ms / 1e6:.0f} GFLOP/s (paper's counts)")
-    del x
+    # one HOOI sweep (Alg. 2) after that ST-HOSVD: time of ST-HOSVD + 1 sweep, minus ST-HOSVD
+    comp = tucker.Compressor(dims, x.dtype, dev, 0.0, ranks=ranks)
+    comp.run_hooi(x, 1, -1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fits = comp.run_hooi(x, 1, -1.0)
+    torch.cuda.synchronize()
+    ms_h = (time.perf_counter() - t0) / steps * 1e3 - ms
+    fl_h = hooi_sweep_flops(dims, ranks)
+    out["200^4->20^4"]["hooi_sweep_ms"] = round(ms_h, 3)
+    out["200^4->20^4"]["hooi_sweep_gflops_paper_count"] = round(fl_h / ms_h / 1e6, 1)
+    out["200^4->20^4"]["hooi_fits"] = fits
+    log(f"[paper] one HOOI sweep: {ms_h:.2f} ms, {fl_h / ms_h / 1e6:.0f} GFLOP/s; fits {fits}")
+    del comp, x
     torch.cuda.empty_cache()
     dims, ranks = (25, 250, 250, 250), (10, 10, 100, 100)
     x = synth.planted_tucker(dims, ranks, rho=1.0, factor_kind="gaussian", noise=1e-6,

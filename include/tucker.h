@@ -192,6 +192,30 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
                      tk_tucker* out, void* ws, size_t ws_bytes, void* stream);
 size_t sthosvd_workspace_bytes(const tk_shape* x, const tk_options* opt);
 
+/* ------------------------------------------------------------------ HOOI
+ * Alg. 2 (HOOI): ST-HOSVD as in sthosvd_compress (eps rule or fixed ranks,
+ * opt->mode_order for that start), then up to max_sweeps sweeps.  A sweep
+ * visits n = 1..N: Y = X x_m U_m^T for every m != n (ascending m), U_n <-
+ * the leading R_n eigenvectors of Y_(n) Y_(n)^T (same eigensolver and sign
+ * rule); after mode N the core G = Y x_N U_N^T.  After the ST-HOSVD and
+ * after every sweep the fit ||X||^2 - ||G||^2 (the model error
+ * ||X - G x {U_n}||^2, Sec. III) is computed in FP64 and read back (one
+ * stream sync per sweep); the iteration stops once a sweep lowers it by at
+ * most tol * ||X||^2 (tol >= 0), or after max_sweeps (tol < 0 runs exactly
+ * max_sweeps).  Precisions as in opt (fixed ranks: no guard).
+ *   out          as for sthosvd_compress; holds the final core and factors;
+ *                discarded[n] = tail sum of mode n's last Gram.
+ *   fits         host, max_sweeps + 1 doubles (may be NULL): fits[0] after
+ *                the ST-HOSVD, fits[k] after sweep k.
+ *   sweeps_done  host (may be NULL): sweeps run.
+ *   ws           at least tucker_hooi_workspace_bytes(x, opt) bytes.
+ * Errors: those of sthosvd_compress, TK_ERR_INVALID_ARG for max_sweeps < 0
+ * or a non-finite tol. */
+size_t tucker_hooi_workspace_bytes(const tk_shape* x, const tk_options* opt);
+int tucker_hooi(const tk_shape* x, const void* x_dev, const tk_options* opt, int max_sweeps,
+                double tol, tk_tucker* out, double* fits, int* sweeps_done, void* ws,
+                size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------ mode order
  * Alg. 1 processes the modes in any order; the order changes the work of
  * the later modes (Sec. VII, mode-order experiment).  Given the extents

@@ -39,7 +39,7 @@ EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "ttm_mode_n", "sthosvd_compres
            "tucker_error_metrics", "error_metrics_workspace_bytes",
            "sthosvd_batch_workspace_bytes", "sthosvd_batch_create", "sthosvd_batch_run",
            "sthosvd_batch_finish", "sthosvd_batch_destroy", "sthosvd_mode_order",
-           "tk_status_string", "tk_last_error")
+           "tucker_hooi_workspace_bytes", "tucker_hooi", "tk_status_string", "tk_last_error")
 
 
 class TuckerError(RuntimeError):
@@ -117,6 +117,11 @@ def library() -> ctypes.CDLL:
         "sthosvd_batch_run": (_int, [_vp, _vp]),
         "sthosvd_batch_finish": (_int, [_vp, _vp]),
         "sthosvd_batch_destroy": (None, [_vp]),
+        "tucker_hooi_workspace_bytes": (_sz, [ctypes.POINTER(Shape), ctypes.POINTER(Options)]),
+        "tucker_hooi": (_int, [ctypes.POINTER(Shape), _vp, ctypes.POINTER(Options), _int,
+                               ctypes.c_double, ctypes.POINTER(Tucker),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), _vp,
+                               _sz, _vp]),
         "sthosvd_mode_order": (_int, [_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64), _int, _int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -327,6 +332,26 @@ class Compressor:
                                           _aligned(self.ws), self.ws_bytes,
                                           _stream(self.device)))
 
+    def run_hooi(self, x: torch.Tensor, max_sweeps: int = 20, tol: float = 0.0) -> list:
+        """Alg. 2 (HOOI) of ``x`` from this compressor's ST-HOSVD settings;
+        returns the fits ||X||^2 - ||G||^2 after the ST-HOSVD and after each
+        sweep (``result()`` then holds the HOOI core and factors)."""
+        if tuple(x.shape) != self.dims or x.dtype != self.dtype:
+            raise ValueError("tensor does not match the compressor's shape/dtype")
+        _require_device(x)
+        lib = library()
+        need = lib.tucker_hooi_workspace_bytes(ctypes.byref(self.shape), ctypes.byref(self.opt))
+        if getattr(self, "hooi_ws_bytes", 0) < need:
+            self.hooi_ws = _workspace(need, self.device)
+            self.hooi_ws_bytes = need
+        fits = (ctypes.c_double * (max_sweeps + 1))()
+        done = ctypes.c_int(0)
+        _check(lib.tucker_hooi(ctypes.byref(self.shape), x.data_ptr(), ctypes.byref(self.opt),
+                               int(max_sweeps), float(tol), ctypes.byref(self.out), fits,
+                               ctypes.byref(done), _aligned(self.hooi_ws), self.hooi_ws_bytes,
+                               _stream(self.device)))
+        return [float(fits[k]) for k in range(done.value + 1)]
+
     def result(self, copy: bool = False) -> TuckerTensor:
         """The last run's outputs: views into this compressor's buffers (valid
         until its next run, and keeping those buffers alive), or with ``copy``
@@ -360,6 +385,18 @@ def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
                    ttm_precision)
     c.run(x)
     return c.result(copy=True)
+
+
+def hooi(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
+         max_sweeps: int = 20, tol: float = 0.0, gram_precision: str = "fp64",
+         ttm_precision: str = "fp64"):
+    """Alg. 2 (HOOI) of ``x`` on its GPU, starting from ST-HOSVD.  Returns
+    ``(TuckerTensor, fits)`` with copies of the outputs; ``fits[0]`` is the
+    ST-HOSVD's ||X||^2 - ||G||^2 and ``fits[k]`` that after sweep k."""
+    c = Compressor(x.shape, x.dtype, x.device, eps, order, ranks, max_ranks, gram_precision,
+                   ttm_precision)
+    fits = c.run_hooi(x, max_sweeps, tol)
+    return c.result(copy=True), fits
 
 
 def _fortran_copy(t: torch.Tensor) -> torch.Tensor:
