@@ -161,30 +161,17 @@ __device__ __forceinline__ double row8_sum(double v) {
     return v;
 }
 
-// JP = 32, 64, 128: A lives in registers during the tridiagonalisation
-// (J <= JP); JP = 0: A lives in the global scratch (J > 128).
+// Householder tridiagonalisation of a symmetric Jr x Jr block held in
+// registers (Jr <= JP): element (i, j) of the block is src[i + ld j].  Its
+// diagonal, off-diagonal and reflector scalars go to d, e, beta at offset
+// koff, and reflector koff + k (length Jr - k - 1) to H[(koff + k) J ..].
+// With koff = 0, Jr = J this is the whole reduction; with koff > 0 it
+// finishes one whose first koff steps ran on the matrix in global memory.
 template <int JP>
-__device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
-    extern __shared__ double smem[];
-    const int J = a.J;
+__device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int ld, int Jr,
+                                             int koff, int J, double* reg, double* red,
+                                             double* d, double* e, double* beta, double* H) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* reg = smem;                        // A (J <= 128) then the LU batch
-    double* sv = smem + region;
-    double* d = sv;              // J
-    double* e = d + J;           // J
-    double* e2 = e + J;          // J (scaled)
-    double* beta = e2 + J;       // J
-    double* pw = beta + J;       // J: A22 x
-    double* lam = pw + J;        // J (descending)
-    double* shift = lam + J;     // J
-    double* dots = shift + J;    // J: v during step 1, scaled d during step 2
-    double* colv = dots + J;     // J: w during step 1
-    double* red = colv + J;      // 64
-    int* misc = (int*)(red + 64);  // [0] = R
-    double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
-    double* X = a.u;                          // column-major J x R
-
-    if constexpr (JP > 0) {
     // ---- 1. Householder tridiagonalisation, A in registers ---------------
     // Thread t owns row i = t / 8 and the columns j = t % 8 + 8 q.  Per column
     // k: the owners of row k form the reflector and publish v; (A22 v)_i is a
@@ -194,12 +181,12 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     // LDS and go to the global scratch once at the end.
     constexpr int NQ = JP / 8;
     const int ri = tid >> 3, rc = tid & 7;
-    const bool rowok = ri < J;
+    const bool rowok = ri < Jr;
     double av[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = rc + 8 * q;
-        av[q] = (rowok && j < J) ? a.s[ri + (size_t)J * j] : 0.0;
+        av[q] = (rowok && j < Jr) ? src[ri + (size_t)ld * j] : 0.0;
     }
     double* Hs = reg;
     constexpr int NS = (JP + 63) / 64;  // per-lane slots of a wave-wide reduction
@@ -211,9 +198,9 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     double* vbuf = red + 64 + 8;
     for (int i = tid; i < 4 * JP; i += kEigThreads) vbuf[i] = 0.0;
     __syncthreads();
-    for (int k = 0; k + 2 < J; ++k) {
-        double* vs = Hs + (size_t)k * JP;        // v = reflector k: v_{k+1} = 1, zero outside k < j < J
-        double* ps = vbuf + (2 + (k & 1)) * JP;  // p = tau A22 v, zero outside k < i < J
+    for (int k = 0; k + 2 < Jr; ++k) {
+        double* vs = Hs + (size_t)k * JP;        // v = reflector k: v_{k+1} = 1, zero outside k < j < Jr
+        double* ps = vbuf + (2 + (k & 1)) * JP;  // p = tau A22 v, zero outside k < i < Jr
         double* sg = red + 40 + (k & 1);         // tau of column k
         if (ri == k) {
             // The owners of row k (= column k, x = its part beyond the diagonal)
@@ -224,7 +211,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int j = rc + 8 * q;
-                sq[q & 3] = fma(((j >= k + 2 && j < J) ? 1.0 : 0.0) * av[q], av[q], sq[q & 3]);
+                sq[q & 3] = fma(((j >= k + 2 && j < Jr) ? 1.0 : 0.0) * av[q], av[q], sq[q & 3]);
             }
             const double sigma = row8_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
             // a_{k,k+1} and a_kk: register (k + 1) / 8 (resp. k / 8) of the
@@ -245,13 +232,13 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int j = rc + 8 * q;
-                vs[j] = j == k + 1 ? 1.0 : ((j > k + 1 && j < J) ? av[q] * inv_v0 : 0.0);
+                vs[j] = j == k + 1 ? 1.0 : ((j > k + 1 && j < Jr) ? av[q] * inv_v0 : 0.0);
             }
             if (rc == 0) {
                 *sg = tau;
-                d[k] = akk;
-                e[k] = alpha;
-                beta[k] = tau;
+                d[koff + k] = akk;
+                e[koff + k] = alpha;
+                beta[koff + k] = tau;
             }
         }
         __syncthreads();
@@ -302,25 +289,54 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         }
     }
     // the trailing 2 x 2 block (or 1 x 1)
-    if (ri >= J - 2 && rowok) {
+    if (ri >= Jr - 2 && rowok) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int j = rc + 8 * q;
-            if (j == ri) d[ri] = av[q];
-            if (ri == J - 2 && j == J - 1) e[J - 2] = av[q];
+            if (j == ri) d[koff + ri] = av[q];
+            if (ri == Jr - 2 && j == Jr - 1) e[koff + Jr - 2] = av[q];
         }
     }
     if (tid == 0) {
-        if (J >= 2) beta[J - 2] = 0.0;
-        e[J - 1] = 0.0;
-        beta[J - 1] = 0.0;
+        if (Jr >= 2) beta[koff + Jr - 2] = 0.0;
+        e[koff + Jr - 1] = 0.0;
+        beta[koff + Jr - 1] = 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) {
-        const int k = idx / J, i = idx - k * J;
-        if (i < J - k - 1) H[idx] = Hs[(size_t)k * JP + k + 1 + i];
+    // reflector koff + k has length J - (koff + k) - 1 = Jr - k - 1
+    for (int idx = tid; idx < (Jr - 2) * Jr; idx += kEigThreads) {
+        const int k = idx / Jr, i = idx - k * Jr;
+        if (i < Jr - k - 1) H[(size_t)(koff + k) * J + i] = Hs[(size_t)k * JP + k + 1 + i];
     }
     __syncthreads();
+}
+
+// JP = 32, 64, 128: A lives in registers during the tridiagonalisation
+// (J <= JP); JP = 0: A lives in the global scratch (J > 128).
+template <int JP>
+__device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
+    extern __shared__ double smem[];
+    const int J = a.J;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* reg = smem;                        // A (J <= 128) then the LU batch
+    double* sv = smem + region;
+    double* d = sv;              // J
+    double* e = d + J;           // J
+    double* e2 = e + J;          // J (scaled)
+    double* beta = e2 + J;       // J
+    double* pw = beta + J;       // J: A22 x
+    double* lam = pw + J;        // J (descending)
+    double* shift = lam + J;     // J
+    double* dots = shift + J;    // J: v during step 1, scaled d during step 2
+    double* colv = dots + J;     // J: w during step 1
+    double* red = colv + J;      // 64
+    int* misc = (int*)(red + 64);  // [0] = R
+    double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
+    double* X = a.u;                          // column-major J x R
+
+    if constexpr (JP > 0) {
+    // ---- 1. Householder tridiagonalisation, A in registers ---------------
+    tridiag_regs<JP>(a.s, J, J, 0, J, reg, red, d, e, beta, H);
     } else {
     double* A = a.scratch;  // row-major J x J
 
@@ -339,7 +355,12 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     double* part = red + 64 + 8;  // [C][rb] = kEigThreads partial sums, after misc
     double* pp = colv;                                    // p
     double* vv = dots;                                    // v
-    for (int k = 0; k + 2 < J; ++k) {
+    // Once the trailing block is 128 x 128 it moves to registers and the
+    // register path finishes the reduction (when the LDS region can hold
+    // its 126 reflectors at pitch 128).
+    const bool hybrid = J > 128 && region >= 126 * 128;
+    const int kend = hybrid ? J - 128 : J - 2;
+    for (int k = 0; k < kend; ++k) {
         const int m = J - k - 1;
         const double* x = A + (size_t)k * J + (k + 1);  // row k, columns k+1.. (= column k)
         // w = A22 x (A22 is symmetric: read column i so a wave's loads are contiguous)
@@ -409,7 +430,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         }
         __syncthreads();
     }
-    if (tid == 0) {
+    if (tid == 0 && !hybrid) {
         if (J >= 2) {
             d[J - 2] = A[(size_t)(J - 2) * J + (J - 2)];
             e[J - 2] = A[(size_t)(J - 2) * J + (J - 1)];
@@ -420,11 +441,13 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         beta[J - 1] = 0.0;
     }
     // reflectors to global scratch: the LDS region is reused from step 4 on
-    for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) {
+    for (int idx = tid; idx < kend * J; idx += kEigThreads) {
         const int k = idx / J, i = idx - k * J;
         if (i < J - k - 1) H[idx] = A[(size_t)(k + 1 + i) * J + k];
     }
     __syncthreads();
+    if (hybrid) tridiag_regs<128>(A + (size_t)kend * J + kend, J, 128, kend, J, reg, red, d, e,
+                                  beta, H);
     }
     if (tid == 0) {
         double gl = DBL_MAX, gu = -DBL_MAX;
