@@ -75,6 +75,10 @@ def _load():
         lib.orc_ttm_entry.argtypes = [_d, ctypes.c_int, _i64, ctypes.c_int, _d, _i64]
         lib.orc_sym_eig.restype = ctypes.c_int
         lib.orc_sym_eig.argtypes = [_d, ctypes.c_int64, _d, _d, ctypes.c_int]
+        lib.orc_qr_r.restype = ctypes.c_int
+        lib.orc_qr_r.argtypes = [_d, ctypes.c_int64, ctypes.c_int64, _d]
+        lib.orc_svd_jacobi.restype = ctypes.c_int
+        lib.orc_svd_jacobi.argtypes = [_d, ctypes.c_int64, _d, _d, ctypes.c_int]
         lib.orc_truncate.restype = ctypes.c_int
         lib.orc_truncate.argtypes = [_d, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, _i64,
                                      _d]
@@ -192,6 +196,38 @@ def sym_eig(s, max_sweeps: int = 50):
     return lam, v, sw
 
 
+def qr_r(a) -> np.ndarray:
+    """R factor (``j x j``, diagonal >= 0, strict lower part zero) of a
+    Householder QR of the ``m x j`` matrix ``a`` (Sec. IX)."""
+    a = np.array(a, dtype=np.float64, order="C", copy=True)
+    m, j = a.shape
+    r = np.empty((j, j))
+    _check(_load().orc_qr_r(_p(a), m, j, _p(r)), "qr_r")
+    return r
+
+
+def svd_jacobi(b, max_sweeps: int = 60):
+    """One-sided Jacobi SVD of a square matrix: ``(sigma_desc, V, sweeps)``;
+    the columns of V are right singular vectors, sign-normalised (largest
+    |entry| positive)."""
+    b = np.array(b, dtype=np.float64, order="C", copy=True)
+    j = b.shape[0]
+    sig = np.empty(j)
+    v = np.empty((j, j))
+    sw = _load().orc_svd_jacobi(_p(b), j, _p(sig), _p(v), max_sweeps)
+    _check(sw, "svd_jacobi")
+    return sig, v, sw
+
+
+def mode_svd_qr(y, n: int):
+    """Leading left singular pairs of ``Y_(n)`` through the QR of
+    ``Y_(n)^T`` (Sec. IX): ``(lambda_desc, U, sweeps)`` with
+    ``lambda_r = sigma_r^2`` and U the right singular vectors of R."""
+    a = np.ascontiguousarray(unfold(y, n).T)
+    sig, v, sw = svd_jacobi(qr_r(a))
+    return sig * sig, v, sw
+
+
 def truncate(lam, tau: float, fixed_rank: int = 0):
     """Rank rule of Alg. 1 -> ``(R, discarded_tail_sum)``."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
@@ -240,6 +276,33 @@ def sthosvd(x, eps: float, order=None, ranks=None) -> TuckerResult:
         eo += dims[k]
     g = core[:int(np.prod(ranks_t))].reshape(ranks_t, order="F").copy()
     return TuckerResult(g, factors, ranks_t, spectra, disc, float(nrm[0]), list(sw))
+
+
+def sthosvd_qr(x, eps: float, order=None, ranks=None) -> TuckerResult:
+    """Alg. 1 with the SVD of each ``Y_(n)`` taken through the QR of
+    ``Y_(n)^T`` instead of the Gram (the stable variant Sec. IX proposes for
+    eps near sqrt(u)): per mode, R of a Householder QR, one-sided Jacobi SVD
+    of R, eigenvalues ``sigma^2``, the same rank rule, U_n = leading right
+    singular vectors of R, ``Y <- Y x_n U_n^T``.  ``sweeps`` counts Jacobi
+    sweeps."""
+    x = _f64_fortran(x)
+    nd = x.ndim
+    order = list(range(nd)) if order is None else [int(k) for k in order]
+    if sorted(order) != list(range(nd)):
+        raise ValueError("order must be a permutation of the modes")
+    nu = norm2(x)
+    tau = eps * eps * nu / nd
+    y = x
+    factors, spectra = [None] * nd, [None] * nd
+    rk, disc, sweeps = [0] * nd, np.zeros(nd), [0] * nd
+    for n in order:
+        lam, v, sw = mode_svd_qr(y, n)
+        r, d = truncate(lam, tau, int(ranks[n]) if ranks is not None else 0)
+        factors[n] = v[:, :r].copy()
+        spectra[n] = lam
+        rk[n], disc[n], sweeps[n] = r, d, sw
+        y = ttm(y, n, factors[n].T)
+    return TuckerResult(y, factors, tuple(rk), spectra, disc, nu, sweeps)
 
 
 @dataclass

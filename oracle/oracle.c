@@ -23,7 +23,11 @@
  *   - rank rule: smallest R with sum_{r>R} lambda_r <= eps^2 ||X||^2 / N
  *     (Alg. 1, rank step), with ||X|| the norm of the ORIGINAL tensor;
  *   - factor U_n = leading R_n eigenvectors; Y <- Y x_n U_n^T (Alg. 1);
- *   - reconstruction X~ = G x {U_n} (Sec. II-C, eq. reconstruct).
+ *   - reconstruction X~ = G x {U_n} (Sec. II-C, eq. reconstruct);
+ *   - the QR-preprocessed alternative of Sec. IX for eps near sqrt(u): the R
+ *     factor of a Householder QR of Y_(n)^T, then an SVD of R by one-sided
+ *     Jacobi; the left singular vectors of Y_(n) are R's right singular
+ *     vectors and lambda_r = sigma_r^2.
  *
  * Matrices in this file are dense row-major arrays (A[r*cols + c]).
  * All sums of long products use pairwise (recursive halving) summation.
@@ -499,3 +503,140 @@ int orc_error_metrics(const double* x, const double* xh, int64_t count, double* 
 
 /* Sum of an array (pairwise); exported for the tail-sum and trace checks. */
 double orc_sum(const double* a, int64_t n) { return pw_sum(a, n); }
+
+/* --------------------------------------------- QR-preprocessed SVD (Sec. IX) */
+
+/*
+ * R factor of a Householder QR of the row-major m x j matrix a (the paper's
+ * stable alternative to the Gram for eps near sqrt(u), Sec. IX: Y_(n)^T is
+ * tall and skinny, so its SVD goes through a QR factorisation first).
+ * Textbook column-by-column reduction (Golub & Van Loan, "Householder QR"):
+ * for k = 0 .. min(m, j) - 1 the reflector I - tau v v^T with v_k = 1 maps
+ * a[k:m, k] to beta e_k, beta = -sign(a_kk) ||a[k:m, k]|| (sign(0) = +),
+ * tau = (beta - a_kk) / beta, v_i = a_ik / (a_kk - beta) for i > k; no
+ * reflection (tau = 0) when a[k+1:m, k] is zero.  It is applied to columns
+ * k+1 .. j-1.  On exit r (row-major j x j) holds R with its strict lower part
+ * zero and each row signed so that its diagonal entry is >= 0 (R is unique
+ * when a has full column rank); rows >= m of R are zero.  a is overwritten.
+ */
+int orc_qr_r(double* a, int64_t m, int64_t j, double* r) {
+    if (!a || !r || m < 1 || j < 1) return ORC_EINVAL;
+    double* col = (double*)malloc(sizeof(double) * m);
+    double* vcol = (double*)malloc(sizeof(double) * m);
+    if (!col || !vcol) { free(col); free(vcol); return ORC_ENOMEM; }
+    const int64_t kmax = m < j ? m : j;
+    for (int64_t k = 0; k < kmax; ++k) {
+        const int64_t len = m - k - 1; /* entries below the diagonal */
+        for (int64_t i = 0; i < len; ++i) col[i] = a[(k + 1 + i) * j + k];
+        const double xnorm = sqrt(pw_sumsq(col, len));
+        if (xnorm == 0.0) continue; /* H_k = I */
+        const double alpha = a[k * j + k];
+        const double nrm = hypot(alpha, xnorm);
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        const double tau = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);
+        for (int64_t i = 0; i < len; ++i) vcol[i] = col[i] * scal;
+        a[k * j + k] = beta;
+        for (int64_t i = 0; i < len; ++i) a[(k + 1 + i) * j + k] = 0.0;
+        for (int64_t c = k + 1; c < j; ++c) {
+            for (int64_t i = 0; i < len; ++i) col[i] = a[(k + 1 + i) * j + c];
+            const double w = tau * (a[k * j + c] + pw_dot(vcol, col, len));
+            a[k * j + c] -= w;
+            for (int64_t i = 0; i < len; ++i) a[(k + 1 + i) * j + c] -= vcol[i] * w;
+        }
+    }
+    for (int64_t i = 0; i < j; ++i) {
+        const double sg = (i < m && a[i * j + i] < 0.0) ? -1.0 : 1.0;
+        for (int64_t c = 0; c < j; ++c)
+            r[i * j + c] = (i < m && c >= i) ? sg * a[i * j + c] : 0.0;
+    }
+    free(col); free(vcol);
+    return ORC_OK;
+}
+
+/*
+ * One-sided (Hestenes) Jacobi SVD of a square j x j matrix b (row-major;
+ * textbook method, e.g. Golub & Van Loan, "one-sided Jacobi"): cyclic
+ * sweeps over column pairs (p, q) rotate columns p and q of b so that they
+ * become orthogonal, and accumulate the same rotations in v, so that on
+ * convergence b_in v = W diag(sigma) with orthonormal W.  A pair is skipped
+ * when |b_p . b_q| <= tol ||b_p|| ||b_q|| (tol = 4 j DBL_EPSILON) or one of
+ * the columns is zero; iteration stops after a sweep with no rotation.
+ * On exit sigma holds the column norms sorted descending (ties in index
+ * order) -- the singular values -- and the columns of v (row-major j x j)
+ * the matching right singular vectors, each signed so that its
+ * largest-magnitude entry (lowest index on ties) is positive.  b is
+ * overwritten.  Returns the sweeps used, or ORC_ENOCONV after max_sweeps.
+ */
+int orc_svd_jacobi(double* b, int64_t j, double* sigma, double* v, int max_sweeps) {
+    if (!b || !sigma || !v || j < 1) return ORC_EINVAL;
+    const double tol = 4.0 * (double)j * 2.220446049250313e-16;
+    double* cp = (double*)malloc(sizeof(double) * j);
+    double* cq = (double*)malloc(sizeof(double) * j);
+    double* nrm = (double*)malloc(sizeof(double) * j);
+    int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * j);
+    double* tmp = (double*)malloc(sizeof(double) * j * j);
+    if (!cp || !cq || !nrm || !perm || !tmp) {
+        free(cp); free(cq); free(nrm); free(perm); free(tmp);
+        return ORC_ENOMEM;
+    }
+    for (int64_t a = 0; a < j; ++a)
+        for (int64_t c = 0; c < j; ++c) v[a * j + c] = (a == c) ? 1.0 : 0.0;
+    int sweep = 0, converged = 0;
+    for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+        int rotated = 0;
+        for (int64_t p = 0; p < j - 1; ++p) {
+            for (int64_t q = p + 1; q < j; ++q) {
+                for (int64_t i = 0; i < j; ++i) { cp[i] = b[i * j + p]; cq[i] = b[i * j + q]; }
+                const double alpha = pw_sumsq(cp, j), beta = pw_sumsq(cq, j);
+                const double gamma = pw_dot(cp, cq, j);
+                if (alpha == 0.0 || beta == 0.0) continue;
+                if (fabs(gamma) <= tol * sqrt(alpha) * sqrt(beta)) continue;
+                rotated = 1;
+                /* rotation zeroing the (p, q) entry of the 2 x 2 Gram
+                   [[alpha, gamma], [gamma, beta]] (same root choice as the
+                   two-sided Jacobi above) */
+                const double zeta = (beta - alpha) / (2.0 * gamma);
+                double t;
+                if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+                else t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                for (int64_t i = 0; i < j; ++i) {
+                    b[i * j + p] = c * cp[i] - s * cq[i];
+                    b[i * j + q] = s * cp[i] + c * cq[i];
+                }
+                for (int64_t i = 0; i < j; ++i) {
+                    const double vp = v[i * j + p], vq = v[i * j + q];
+                    v[i * j + p] = c * vp - s * vq;
+                    v[i * j + q] = s * vp + c * vq;
+                }
+            }
+        }
+        if (!rotated) { converged = 1; break; }
+    }
+    for (int64_t p = 0; p < j; ++p) {
+        for (int64_t i = 0; i < j; ++i) cp[i] = b[i * j + p];
+        nrm[p] = sqrt(pw_sumsq(cp, j));
+    }
+    for (int64_t a = 0; a < j; ++a) perm[a] = a;
+    for (int64_t a = 1; a < j; ++a) { /* stable insertion sort, descending */
+        int64_t cur = perm[a];
+        int64_t c = a - 1;
+        while (c >= 0 && nrm[perm[c]] < nrm[cur]) { perm[c + 1] = perm[c]; --c; }
+        perm[c + 1] = cur;
+    }
+    for (int64_t a = 0; a < j; ++a) sigma[a] = nrm[perm[a]];
+    for (int64_t i = 0; i < j; ++i)
+        for (int64_t a = 0; a < j; ++a) tmp[i * j + a] = v[i * j + perm[a]];
+    for (int64_t a = 0; a < j; ++a) { /* sign rule */
+        int64_t best = 0;
+        for (int64_t i = 1; i < j; ++i)
+            if (fabs(tmp[i * j + a]) > fabs(tmp[best * j + a])) best = i;
+        if (tmp[best * j + a] < 0)
+            for (int64_t i = 0; i < j; ++i) tmp[i * j + a] = -tmp[i * j + a];
+    }
+    memcpy(v, tmp, sizeof(double) * j * j);
+    free(cp); free(cq); free(nrm); free(perm); free(tmp);
+    return converged ? sweep : ORC_ENOCONV;
+}
