@@ -87,7 +87,19 @@ typedef enum tk_gram_precision {
      * with J <= 32 whose unfolding has at most 2^26 elements take the FP64
      * Gram directly: at J <= 32 it costs no more on FP32 data (arithmetic
      * intensity below the FP64 matrix-core ridge) and needs no guard. */
-    TK_GRAM_SPLIT_BF16 = 1
+    TK_GRAM_SPLIT_BF16 = 1,
+    /* No Gram (sthosvd_compress only; FP64 or FP32 input, dims[n] <=
+     * TK_QR_MAX_MODE_DIM at every mode): the singular values of Y_(n) come
+     * from a QR of Y_(n)^T, the stable alternative Sec. IX proposes for eps
+     * near sqrt(u).  Per mode: R = qr_r_mode_n(Y, n); the symmetric matrix
+     * [[0, R^T], [R, 0]] goes through the same FP64 eigensolver, whose
+     * leading J_n eigenvalues are sigma_r(R) = sigma_r(Y_(n)) with absolute
+     * error about u sigma_1 (the Gram's eigenvalues carry about u sigma_1^2,
+     * which hides every sigma_r below sqrt(u) sigma_1); lambda_r = sigma_r^2
+     * feeds the same rank rule; U_n = the first J_n entries of the leading
+     * eigenvectors, orthonormalised (Gram-Schmidt twice) and signed by the
+     * same rule.  Costs a few times the FP64 Gram path. */
+    TK_SVD_QR = 2
 } tk_gram_precision;
 
 /* Arithmetic of the tensor-times-matrix product. */
@@ -123,6 +135,34 @@ typedef struct tk_shape {
 int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, double* s_dev,
                 double* sumsq_dev, void* ws, size_t ws_bytes, void* stream);
 size_t gram_workspace_bytes(const tk_shape* y, int mode, int precision);
+
+/* -------------------------------------------------------------------- QR */
+
+/* Largest mode extent of the QR path (R is kept in one workgroup's LDS). */
+#define TK_QR_MAX_MODE_DIM 128
+
+/*
+ * R factor of a Householder QR of the tall and skinny A = Y_(n)^T (Sec. IX:
+ * the stable way to the singular values of Y_(n) when eps nears sqrt(u);
+ * A has prod_{m != n} J_m rows and J_n columns).  Rows of A are absorbed in
+ * tiles into running factors, which are then combined by a reduction tree
+ * (the same Householder step applied to stacked factors); the split of rows
+ * does not depend on the device, so the result is deterministic.
+ *   y, y_dev    input tensor (F64, or F32 widened exactly); dims[mode] <=
+ *               TK_QR_MAX_MODE_DIM.
+ *   r_dev       out: J_n x J_n FP64 column-major, upper triangular (strict
+ *               lower part written as 0), each row signed so that its
+ *               diagonal entry is >= 0; Y_(n) Y_(n)^T = R^T R in exact
+ *               arithmetic.  If A has fewer rows than columns the trailing
+ *               rows of R are zero.
+ *   sumsq_dev   out (may be NULL): one FP64, ||Y||^2 summed in a fixed order.
+ *   ws          at least qr_workspace_bytes(y, mode) bytes, 256-B aligned.
+ * Entries whose square under- or overflows FP64 (|x| outside about
+ * [1e-154, 1e154]) are outside the supported range, as for the Gram.
+ */
+int qr_r_mode_n(const tk_shape* y, const void* y_dev, int mode, double* r_dev,
+                double* sumsq_dev, void* ws, size_t ws_bytes, void* stream);
+size_t qr_workspace_bytes(const tk_shape* y, int mode);
 
 /* ------------------------------------------------------------------- TTM */
 

@@ -152,6 +152,34 @@ int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, d
                        (hipStream_t)stream);
 }
 
+// -------------------------------------------------------------------- QR
+
+static int check_qr_args(const tk_shape* y, int mode) {
+    TK_TRY(check_shape(y, "qr_r_mode_n"));
+    if (mode < 0 || mode >= y->ndim)
+        return fail(TK_ERR_INVALID_ARG, "qr_r_mode_n: mode %d outside [0, %d)", mode, y->ndim);
+    if (y->dims[mode] > TK_QR_MAX_MODE_DIM)
+        return fail(TK_ERR_UNSUPPORTED, "qr_r_mode_n: dims[%d] = %lld exceeds %d", mode,
+                    (long long)y->dims[mode], TK_QR_MAX_MODE_DIM);
+    return TK_OK;
+}
+
+size_t qr_workspace_bytes(const tk_shape* y, int mode) {
+    if (check_qr_args(y, mode) != TK_OK) return 0;
+    ModeView v = mode_view(y->dims, y->ndim, mode);
+    return qr_workspace_doubles(plan_qr(v)) * sizeof(double) + 256;
+}
+
+int qr_r_mode_n(const tk_shape* y, const void* y_dev, int mode, double* r_dev,
+                double* sumsq_dev, void* ws, size_t ws_bytes, void* stream) {
+    TK_TRY(check_qr_args(y, mode));
+    if (!y_dev || !r_dev) return fail(TK_ERR_INVALID_ARG, "qr_r_mode_n: NULL device pointer");
+    TK_TRY(check_ws(ws, ws_bytes, qr_workspace_bytes(y, mode), "qr_r_mode_n"));
+    ModeView v = mode_view(y->dims, y->ndim, mode);
+    return launch_tsqr(y_dev, y->dtype, v, plan_qr(v), (double*)ws, r_dev, sumsq_dev,
+                       (hipStream_t)stream);
+}
+
 // ------------------------------------------------------------------- TTM
 
 static int check_ttm_args(const tk_shape* y, int mode, int64_t m_rows, int64_t m_cols,
@@ -202,6 +230,7 @@ struct SthosvdPlan {
     int64_t cap[TK_MAX_NDIM];   // rank capacity per mode
     size_t y_bytes[2];          // ping-pong buffers
     size_t gram_bytes, s_bytes, eig_bytes, lam_bytes;
+    size_t qr_bytes, r_bytes, z_bytes;  // TK_SVD_QR only
     size_t total;
 };
 
@@ -242,13 +271,19 @@ static int check_options(const tk_shape* x, const tk_options* opt, SthosvdPlan* 
         }
         pl->cap[n] = c;
     }
-    if (opt->gram_precision != TK_GRAM_FP64 && opt->gram_precision != TK_GRAM_SPLIT_BF16)
+    const bool qr = opt->gram_precision == TK_SVD_QR;
+    if (opt->gram_precision != TK_GRAM_FP64 && opt->gram_precision != TK_GRAM_SPLIT_BF16 && !qr)
         return fail(TK_ERR_INVALID_ARG, "sthosvd_compress: unknown gram precision");
+    if (qr)
+        for (int n = 0; n < N; ++n)
+            if (x->dims[n] > TK_QR_MAX_MODE_DIM)
+                return fail(TK_ERR_UNSUPPORTED, "sthosvd_compress: the QR path needs dims[%d] "
+                            "<= %d", n, TK_QR_MAX_MODE_DIM);
     if (opt->ttm_precision != TK_TTM_FP64 && opt->ttm_precision != TK_TTM_BF16 &&
         opt->ttm_precision != TK_TTM_BF16X3)
         return fail(TK_ERR_INVALID_ARG, "sthosvd_compress: unknown ttm precision");
     if (x->dtype != TK_F32 &&
-        (opt->gram_precision != TK_GRAM_FP64 || opt->ttm_precision != TK_TTM_FP64))
+        (opt->gram_precision == TK_GRAM_SPLIT_BF16 || opt->ttm_precision != TK_TTM_FP64))
         return fail(TK_ERR_UNSUPPORTED, "sthosvd_compress: bf16 paths need FP32 storage");
 
     // workspace plan: sizes at the rank capacities
@@ -263,10 +298,10 @@ static int check_options(const tk_shape* x, const tk_options* opt, SthosvdPlan* 
         ModeView v = mode_view(cur, N, n);
         // the tile count (hence the partial count) depends on the ranks found
         // at run time, so size for the grid cap of this mode's extent
-        GramPlan gp = plan_gram(v, opt->gram_precision, (int)b);
-        size_t gb = gp.partial_bound;
+        GramPlan gp = plan_gram(v, qr ? TK_GRAM_FP64 : opt->gram_precision, (int)b);
+        size_t gb = qr ? 0 : gp.partial_bound;
         if (gb > pl->gram_bytes) pl->gram_bytes = gb;
-        if (opt->gram_precision != TK_GRAM_FP64) {  // room for the guard's FP64 Gram
+        if (opt->gram_precision == TK_GRAM_SPLIT_BF16) {  // room for the guard's FP64 Gram
             GramPlan g64 = plan_gram(v, TK_GRAM_FP64, (int)b);
             if (g64.partial_bound > pl->gram_bytes) pl->gram_bytes = g64.partial_bound;
         }
@@ -279,8 +314,13 @@ static int check_options(const tk_shape* x, const tk_options* opt, SthosvdPlan* 
             if (by > pl->y_bytes[s & 1]) pl->y_bytes[s & 1] = by;
         }
     }
-    pl->s_bytes = (size_t)jmax * jmax * sizeof(double);
-    pl->eig_bytes = eig_scratch_doubles(jmax) * sizeof(double);
+    // the QR path hands the eigensolver 2J x 2J matrices
+    const int jeig = qr ? 2 * jmax : jmax;
+    pl->s_bytes = (size_t)jeig * jeig * sizeof(double);
+    pl->eig_bytes = eig_scratch_doubles(jeig) * sizeof(double);
+    pl->qr_bytes = qr ? qr_workspace_bound_doubles(jmax) * sizeof(double) : 0;
+    pl->r_bytes = qr ? (size_t)jmax * jmax * sizeof(double) : 0;
+    pl->z_bytes = qr ? (size_t)2 * jmax * jmax * sizeof(double) : 0;
     int64_t sumdims = 0;
     for (int k = 0; k < N; ++k) sumdims += x->dims[k];
     pl->lam_bytes = (size_t)sumdims * sizeof(double);
@@ -292,6 +332,9 @@ static int check_options(const tk_shape* x, const tk_options* opt, SthosvdPlan* 
     c.take(pl->eig_bytes);
     c.take(pl->lam_bytes);
     c.take(64 * sizeof(double));  // scalars
+    c.take(pl->qr_bytes);
+    c.take(pl->r_bytes);
+    c.take(pl->z_bytes);
     pl->total = c.used + 256;
     return TK_OK;
 }
@@ -324,6 +367,10 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     double* eig_ws = (double*)c.take(pl.eig_bytes);
     double* lam_ws = (double*)c.take(pl.lam_bytes);
     double* scal = (double*)c.take(64 * sizeof(double));
+    double* qr_ws = (double*)c.take(pl.qr_bytes);
+    double* r_ws = (double*)c.take(pl.r_bytes);
+    double* z_ws = (double*)c.take(pl.z_bytes);
+    const bool qr = opt->gram_precision == TK_SVD_QR;
     double* nu_dev = scal;                       // [0]
     double* disc_dev = scal + 1;                 // [1..8]
     int64_t* rank_dev = (int64_t*)(scal + 16);   // [16..23]
@@ -361,24 +408,34 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         if (gprec == TK_GRAM_SPLIT_BF16 && v.J <= 32 &&
             (double)v.L * (double)v.J * (double)v.B <= kSmallFp64GramElems)
             gprec = TK_GRAM_FP64;
-        TK_TRY(launch_gram(ycur, x->dtype, v, gprec, S, s == 0 ? nu_dev : nullptr, gram_ws,
-                           pl.gram_bytes, st));
+        if (qr) {
+            // R of Y_(n)^T, then the Jordan-Wielandt matrix [[0, R^T], [R, 0]]
+            TK_TRY(launch_tsqr(ycur, x->dtype, v, plan_qr(v), qr_ws, r_ws,
+                               s == 0 ? nu_dev : nullptr, st));
+            TK_TRY(launch_jw(r_ws, v.J, S, st));
+        } else {
+            TK_TRY(launch_gram(ycur, x->dtype, v, gprec, S, s == 0 ? nu_dev : nullptr, gram_ws,
+                               pl.gram_bytes, st));
+        }
         EigArgs ea;
         ea.s = S;
-        ea.J = v.J;
+        ea.J = qr ? 2 * v.J : v.J;
+        ea.aug = qr ? 1 : 0;
         ea.nu = nu_dev;
         ea.eps2_over_n = eps2n;
         ea.fixed_rank = opt->fixed_ranks ? (int)opt->fixed_ranks[n] : 0;
         ea.max_rank = (int)pl.cap[n];
         ea.lambda = lam_all + lam_off[n];
-        ea.u = out->factors_dev[n];
+        ea.u = qr ? z_ws : out->factors_dev[n];
         ea.rank_out = rank_dev + n;
         ea.disc_out = disc_dev + n;
         ea.flags = flags_dev;
         ea.scratch = eig_ws;
-        const bool mixed = gprec != TK_GRAM_FP64;
+        const bool mixed = gprec == TK_GRAM_SPLIT_BF16;
         ea.guard = (mixed && !opt->fixed_ranks) ? kSplitGramGuard : 0.0;
         TK_TRY(launch_eig(ea, st));
+        if (qr) TK_TRY(launch_jw_extract(z_ws, v.J, (int)pl.cap[n], rank_dev + n,
+                                         out->factors_dev[n], st));
 
         int64_t R;
         if (opt->fixed_ranks && s > 0) {

@@ -507,20 +507,26 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         }
     }
     __syncthreads();
-    for (int i = tid; i < J; i += kEigThreads) a.lambda[i] = lam[i];
+    // Jordan-Wielandt input: the leading half of the spectrum is sigma(R)
+    const int Jv = a.aug ? J / 2 : J;
+    auto val = [&](int r) {
+        const double l = fmax(lam[r], 0.0);
+        return a.aug ? l * l : l;
+    };
+    for (int i = tid; i < Jv; i += kEigThreads) a.lambda[i] = a.aug ? val(i) : lam[i];
 
     // ---- 3. rank rule ---------------------------------------------------
     if (tid == 0) {
         int R;
         double tail = 0.0;
         if (a.fixed_rank > 0) {
-            R = a.fixed_rank < J ? a.fixed_rank : J;
-            for (int r = J - 1; r >= R; --r) tail += fmax(lam[r], 0.0);
+            R = a.fixed_rank < Jv ? a.fixed_rank : Jv;
+            for (int r = Jv - 1; r >= R; --r) tail += val(r);
         } else {
             const double tau = a.eps2_over_n * (*a.nu);
-            R = J;
-            while (R > 1 && tail + fmax(lam[R - 1], 0.0) <= tau) {
-                tail += fmax(lam[R - 1], 0.0);
+            R = Jv;
+            while (R > 1 && tail + val(R - 1) <= tau) {
+                tail += val(R - 1);
                 --R;
             }
             if (a.guard > 0.0) {

@@ -98,7 +98,8 @@ int read_back(const double* dev, size_t n, double* host, hipStream_t st) {
 extern "C" {
 
 size_t tucker_hooi_workspace_bytes(const tk_shape* x, const tk_options* opt) {
-    if (!x || !opt || sthosvd_workspace_bytes(x, opt) == 0) return 0;
+    if (!x || !opt || opt->gram_precision == TK_SVD_QR || sthosvd_workspace_bytes(x, opt) == 0)
+        return 0;
     return plan_hooi(x, opt).total;
 }
 
@@ -108,6 +109,9 @@ int tucker_hooi(const tk_shape* x, const void* x_dev, const tk_options* opt, int
     if (max_sweeps < 0) return fail(TK_ERR_INVALID_ARG, "tucker_hooi: max_sweeps %d < 0", max_sweeps);
     if (!std::isfinite(tol)) return fail(TK_ERR_INVALID_ARG, "tucker_hooi: tol is not finite");
     if (!x || !opt || !out) return fail(TK_ERR_INVALID_ARG, "tucker_hooi: NULL argument");
+    if (opt->gram_precision == TK_SVD_QR)
+        return fail(TK_ERR_UNSUPPORTED, "tucker_hooi: the QR path is provided by "
+                    "sthosvd_compress only");
     if (sthosvd_workspace_bytes(x, opt) == 0)  // invalid shape or options: let compress report
         return sthosvd_compress(x, x_dev, opt, out, ws, ws_bytes, stream);
     const HooiPlan pl = plan_hooi(x, opt);

@@ -178,7 +178,27 @@ struct EigArgs {
     double* scratch;       // eig_scratch_doubles(J)
     double guard = 0.0;    // > 0: flag a rank decision closer to the threshold than
                            // guard * trace * R (J - R) / J^2 (mixed-precision Grams)
+    int aug = 0;           // 1: s is [[0, R^T], [R, 0]] (J = 2 J_R): its leading J_R
+                           // eigenvalues are sigma_i(R); lambda (J_R values) and the
+                           // rank rule use sigma_i^2, u receives 2 J_R x R vectors
 };
+
+// Householder QR (R factor only) of A = Y_(n)^T through a reduction tree.
+struct QrPlan {
+    int JC, BR, levels;           // column class (32/64/128), tile rows, tree levels
+    int P[16];                    // workgroups per level
+    int64_t rows_per_wg[16];
+    size_t part_doubles[2];       // ping-pong partial factors
+    size_t ss_doubles;            // first-level sums of squares
+};
+QrPlan plan_qr(const ModeView& v);
+size_t qr_workspace_doubles(const QrPlan& pl);
+size_t qr_workspace_bound_doubles(int J);
+int launch_tsqr(const void* y, int dtype, const ModeView& v, const QrPlan& pl, double* ws,
+                double* r_out, double* sumsq, hipStream_t st);
+int launch_jw(const double* r, int J, double* m, hipStream_t st);
+int launch_jw_extract(const double* z, int J, int max_rank, const int64_t* rank, double* u,
+                      hipStream_t st);
 
 // Error scale of the split-bf16 Gram in the trailing eigenvalue sums, per
 // unit of trace * R (J - R) / J^2: signal/tail coupling through the bf16

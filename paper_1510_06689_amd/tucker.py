@@ -27,14 +27,15 @@ LIB_PATH = os.path.join(_HERE, "libtucker.so")
 
 MAX_NDIM = 8
 F64, F32 = 0, 1
-GRAM_PRECISIONS = {"fp64": 0, "split_bf16": 1}
+GRAM_PRECISIONS = {"fp64": 0, "split_bf16": 1, "qr": 2}
 TTM_PRECISIONS = {"fp64": 0, "bf16": 1, "bf16x3": 2}
 _TTM_NAMES = {v: k for k, v in TTM_PRECISIONS.items()}
 STATUS = {0: "TK_OK", -1: "TK_ERR_INVALID_ARG", -2: "TK_ERR_UNSUPPORTED",
           -3: "TK_ERR_WORKSPACE", -4: "TK_ERR_HIP", -5: "TK_ERR_NONFINITE",
           -6: "TK_ERR_EIG_NO_CONVERGENCE", -7: "TK_ERR_CAPACITY"}
 
-EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "ttm_mode_n", "sthosvd_compress",
+EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "qr_r_mode_n", "qr_workspace_bytes",
+           "ttm_mode_n", "sthosvd_compress",
            "sthosvd_workspace_bytes", "tucker_reconstruct", "reconstruct_workspace_bytes",
            "tucker_error_metrics", "error_metrics_workspace_bytes",
            "sthosvd_batch_workspace_bytes", "sthosvd_batch_create", "sthosvd_batch_run",
@@ -98,6 +99,8 @@ def library() -> ctypes.CDLL:
     sig = {
         "gram_mode_n": (_int, [_pshape, _vp, _int, _int, _vp, _vp, _vp, _sz, _vp]),
         "gram_workspace_bytes": (_sz, [_pshape, _int, _int]),
+        "qr_r_mode_n": (_int, [_pshape, _vp, _int, _vp, _vp, _vp, _sz, _vp]),
+        "qr_workspace_bytes": (_sz, [_pshape, _int]),
         "ttm_mode_n": (_int, [_pshape, _vp, _int, _vp, _i64, _i64, _int, _int, _vp, _vp]),
         "sthosvd_compress": (_int, [_pshape, _vp, ctypes.POINTER(Options),
                                     ctypes.POINTER(Tucker), _vp, _sz, _vp]),
@@ -228,6 +231,24 @@ def gram(y: torch.Tensor, mode: int, precision: str = "fp64"):
     return s, sumsq
 
 
+def qr_r(y: torch.Tensor, mode: int):
+    """R factor (FP64 J x J, column-major, upper triangular, diagonal >= 0) of
+    a Householder QR of ``Y_(n)^T`` (Sec. IX) and ``||Y||^2``."""
+    _require_device(y)
+    lib = library()
+    sh = shape_of(y)
+    need = lib.qr_workspace_bytes(ctypes.byref(sh), mode)
+    if need == 0:
+        _check(lib.qr_r_mode_n(ctypes.byref(sh), y.data_ptr(), mode, None, None, None, 0, None))
+    j = y.shape[mode]
+    r = empty_colmajor(j, j, y.device)
+    sumsq = torch.empty((), dtype=torch.float64, device=y.device)
+    ws = _workspace(need, y.device)
+    _check(lib.qr_r_mode_n(ctypes.byref(sh), y.data_ptr(), mode, r.data_ptr(), sumsq.data_ptr(),
+                           _aligned(ws), need, _stream(y.device)))
+    return r, sumsq
+
+
 def ttm(y: torch.Tensor, mode: int, m: torch.Tensor, transpose: bool = True,
         precision: str = "fp64") -> torch.Tensor:
     """``Z = Y x_n op(M)``; ``op(M) = M^T`` when ``transpose`` (M is J_n x K),
@@ -341,11 +362,15 @@ class Compressor:
         _require_device(x)
         lib = library()
         need = lib.tucker_hooi_workspace_bytes(ctypes.byref(self.shape), ctypes.byref(self.opt))
+        fits = (ctypes.c_double * (max_sweeps + 1))()
+        done = ctypes.c_int(0)
+        if need == 0:  # unsupported options: let the entry point report why
+            _check(lib.tucker_hooi(ctypes.byref(self.shape), x.data_ptr(), ctypes.byref(self.opt),
+                                   int(max_sweeps), float(tol), ctypes.byref(self.out), fits,
+                                   ctypes.byref(done), None, 0, _stream(self.device)))
         if getattr(self, "hooi_ws_bytes", 0) < need:
             self.hooi_ws = _workspace(need, self.device)
             self.hooi_ws_bytes = need
-        fits = (ctypes.c_double * (max_sweeps + 1))()
-        done = ctypes.c_int(0)
         _check(lib.tucker_hooi(ctypes.byref(self.shape), x.data_ptr(), ctypes.byref(self.opt),
                                int(max_sweeps), float(tol), ctypes.byref(self.out), fits,
                                ctypes.byref(done), _aligned(self.hooi_ws), self.hooi_ws_bytes,

@@ -76,6 +76,45 @@ def test_gram_validation():
     assert lib.gram_mode_n(ctypes.byref(wrong_dtype), FAKE, 0, 0, FAKE, None, None, 0, None) == -1
 
 
+def test_qr_validation():
+    lib = tk.library()
+    s = shape([4, 5, 6])
+    assert lib.qr_r_mode_n(None, FAKE, 0, FAKE, None, None, 0, None) == -1
+    assert lib.qr_r_mode_n(ctypes.byref(s), FAKE, 3, FAKE, None, None, 0, None) == -1
+    assert "mode" in last_error()
+    assert lib.qr_r_mode_n(ctypes.byref(s), None, 0, FAKE, None, None, 0, None) == -1
+    assert lib.qr_r_mode_n(ctypes.byref(s), FAKE, 0, None, None, None, 0, None) == -1
+    need = lib.qr_workspace_bytes(ctypes.byref(s), 0)
+    assert need > 0
+    assert lib.qr_r_mode_n(ctypes.byref(s), FAKE, 0, FAKE, None, FAKE, need - 1, None) == -3
+    assert lib.qr_r_mode_n(ctypes.byref(s), FAKE, 0, FAKE, None, FAKE + 8, need, None) == -3
+    wide = shape([129, 2])
+    assert lib.qr_workspace_bytes(ctypes.byref(wide), 0) == 0
+    assert lib.qr_r_mode_n(ctypes.byref(wide), FAKE, 0, FAKE, None, None, 0, None) == -2
+    assert lib.qr_workspace_bytes(ctypes.byref(wide), 1) > 0  # the narrow mode is fine
+
+
+def test_qr_option_validation():
+    lib = tk.library()
+    keep = []
+    o = tk._options(3, 1e-7, None, None, None, "qr", "fp64", keep)
+    s = shape([4, 5, 6])
+    assert lib.sthosvd_workspace_bytes(ctypes.byref(s), ctypes.byref(o)) > 0
+    s32 = shape([4, 5, 6], dtype=tk.F32)
+    assert lib.sthosvd_workspace_bytes(ctypes.byref(s32), ctypes.byref(o)) > 0
+    wide = shape([4, 129, 6])
+    assert lib.sthosvd_workspace_bytes(ctypes.byref(wide), ctypes.byref(o)) == 0
+    out = tk.Tucker()
+    assert lib.sthosvd_compress(ctypes.byref(wide), FAKE, ctypes.byref(o), ctypes.byref(out),
+                                None, 0, None) == -2
+    # HOOI runs its sweeps on Grams: the QR option is rejected there
+    assert lib.tucker_hooi_workspace_bytes(ctypes.byref(s), ctypes.byref(o)) == 0
+    fits = (ctypes.c_double * 2)()
+    done = ctypes.c_int(0)
+    assert lib.tucker_hooi(ctypes.byref(s), FAKE, ctypes.byref(o), 1, 0.0, ctypes.byref(out),
+                           fits, ctypes.byref(done), None, 0, None) == -2
+
+
 def test_ttm_validation():
     lib = tk.library()
     s = shape([4, 5, 6])

@@ -1,0 +1,165 @@
+"""QR-preprocessed SVD path (Sec. IX) on the GPU against the oracle.
+
+* qr_r_mode_n: R element by element against the oracle's Householder R of
+  the explicit Y_(n)^T (both with a non-negative diagonal, which makes R
+  unique for full column rank), over the three column classes, one and
+  several tiles, ragged row counts, L = 1 and L > 1, a reduction tree of
+  one, two and three levels, fewer rows than columns, J = 1, FP32 input;
+  ||Y||^2 against the oracle's.
+* sthosvd_compress with TK_SVD_QR against oracle.sthosvd_qr: ranks, the
+  spectra sigma_r^2, factors, core, discarded sums.
+* eps near sqrt(u) on tensors whose spectra are known exactly (Hadamard
+  factors, superdiagonal core): the QR path finds the exact ranks and
+  resolves singular values down to about u sigma_1.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.linalg import hadamard
+
+import oracle
+import synth
+from paper_1510_06689_amd import tucker
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps
+
+
+def np_unfold(x, n):
+    return np.reshape(np.moveaxis(x, n, 0), (x.shape[n], -1), order="F")
+
+
+def r_tolerance(a):
+    # both sides are backward stable Householder factorisations of a
+    # well-conditioned A; their R differ by about (rows) u ||A||
+    return 64.0 * math.sqrt(a.shape[0]) * U * np.linalg.norm(a)
+
+
+QR_CASES = [
+    ((40, 37, 33), 0, torch.float64),    # J = 40 (class 64), L = 1, 3 tiles -> 2 levels
+    ((40, 37, 33), 1, torch.float64),    # L = 40
+    ((40, 37, 33), 2, torch.float64),    # L = 1480, B = 1
+    ((128, 64, 48), 0, torch.float64),   # J = 128, 12 tiles -> 3 levels
+    ((5, 128, 700), 1, torch.float64),   # L = 5, ragged rows
+    ((17, 3000), 0, torch.float64),      # class 32, 3 tiles
+    ((32, 32, 32, 64), 0, torch.float64),  # 64 first-level workgroups
+    ((100, 3), 0, torch.float64),        # 3 rows < 100 columns
+    ((1, 500), 0, torch.float64),        # J = 1
+    ((64, 50, 40), 2, torch.float32),    # FP32 input
+    ((96, 9, 70), 0, torch.float32),
+]
+
+
+@pytest.mark.parametrize("dims,mode,dtype", QR_CASES)
+def test_qr_r_matches_oracle(dims, mode, dtype):
+    say(f"qr_r {dims} mode {mode} {dtype}")
+    x = synth.random_tensor(dims, seed=sum(dims) + mode, dtype=dtype)
+    xh = x.to(torch.float64).numpy()
+    r, ss = tucker.qr_r(to_dev(x), mode)
+    r = r.cpu().numpy()
+    a = np.ascontiguousarray(np_unfold(xh, mode).T)
+    ref = oracle.qr_r(a)
+    assert np.all(np.tril(r, -1) == 0)
+    assert np.all(np.diag(r) >= 0)
+    np.testing.assert_allclose(r, ref, rtol=0, atol=r_tolerance(a))
+    nu = oracle.norm2(xh)
+    assert abs(float(ss) - nu) <= 1e-13 * nu
+
+
+def test_qr_r_identity_against_gram():
+    # R^T R = Y_(n) Y_(n)^T on a wide row range: the same property at any size
+    x = synth.random_tensor((64, 512, 600), seed=5)
+    r, _ = tucker.qr_r(to_dev(x), 0)
+    r = r.cpu().numpy()
+    s = oracle.gram(x.numpy(), 0)
+    assert np.abs(r.T @ r - s).max() <= 64 * math.sqrt(512 * 600) * U * np.abs(s).max()
+
+
+def _planted(dims, ranks, seed, noise=1e-3, dtype=torch.float64):
+    return synth.planted_tucker(dims, ranks, rho=0.8, factor_kind="gaussian", noise=noise,
+                                noise_mode="exact", seed=seed, dtype=dtype)
+
+
+ST_CASES = [((14, 12, 10), (4, 4, 3), 0.05, None, torch.float64),
+            ((40, 33, 37, 6), (5, 4, 6, 2), 0.01, (3, 1, 0, 2), torch.float64),
+            ((130 - 2, 20, 9), (6, 5, 3), 0.02, None, torch.float64),
+            ((64, 48, 20), (8, 6, 4), 0.01, None, torch.float32)]
+
+
+@pytest.mark.parametrize("dims,ranks,eps,order,dtype", ST_CASES)
+def test_sthosvd_qr_matches_oracle(dims, ranks, eps, order, dtype):
+    say(f"sthosvd qr {dims} eps {eps} order {order} {dtype}")
+    x = _planted(dims, ranks, seed=len(dims) * 7 + dims[0], dtype=dtype)
+    xh = x.to(torch.float64).numpy()
+    res = tucker.sthosvd(to_dev(x), eps, order=order, gram_precision="qr")
+    ref = oracle.sthosvd_qr(xh, eps, order=order)
+    assert res.ranks == ref.ranks
+    nu = ref.norm2
+    s1 = math.sqrt(nu)
+    first = (order or list(range(len(dims))))[0]
+    # FP32 storage: after the first mode the GPU's Y is rounded to FP32 (the
+    # oracle keeps FP64), which moves every sigma by up to about u32 ||Y||
+    u32 = 2.0 ** -24 if dtype == torch.float32 else 0.0
+    for n in range(len(dims)):
+        lam = res.eigvals[n].cpu().numpy()
+        sig_ref = np.sqrt(np.maximum(ref.eigvals[n], 0))
+        rnd = 0.0 if n == first else 4 * u32 * s1
+        tol = 64 * dims[n] * U * s1 + rnd
+        err = np.abs(np.sqrt(np.maximum(lam, 0)) - sig_ref).max()
+        assert err <= tol, (n, err, tol)
+        u = res.factors[n].cpu().numpy()
+        assert np.abs(u.T @ u - np.eye(u.shape[1])).max() <= 1e-13
+        assert np.abs(u - ref.factors[n]).max() <= (1e-8 if rnd == 0 else 1e-4)
+        assert abs(res.discarded[n] - ref.discarded[n]) <= 1e-10 * nu + 2 * rnd * s1
+    core = res.core.cpu().to(torch.float64).numpy()
+    assert np.abs(core - ref.core).max() <= (1e-8 if dtype == torch.float64 else 1e-5) * s1
+
+
+def _superdiagonal(i, g):
+    # X = sum_r g_r q_r o q_r o q_r, q_r = columns of Hadamard(i)/sqrt(i):
+    # every unfolding has the singular values g
+    q = hadamard(i).astype(np.float64) / math.sqrt(i)
+    return np.asfortranarray(np.einsum("r,ir,jr,kr->ijk", g, q, q, q))
+
+
+def _sequential_ranks(g, tau, nmodes=3):
+    # truncating one mode of the superdiagonal tensor keeps g[:R] in the next
+    ranks, top = [], len(g)
+    for _ in range(nmodes):
+        tails = [float(np.sum(g[r:top] ** 2)) for r in range(top + 1)]
+        r = next(r for r in range(1, top + 1) if tails[r] <= tau)
+        ranks.append(r)
+        top = r
+    return tuple(ranks)
+
+
+@pytest.mark.parametrize("i,step", [(16, 2.0), (64, 0.5)])
+def test_qr_path_exact_ranks_near_sqrt_u(i, step):
+    g = 2.0 ** (-step * np.arange(i))
+    x = _superdiagonal(i, g)
+    nu = float(np.sum(g * g))
+    eps = 2.0 ** -24
+    tau = eps * eps * nu / 3
+    tails = np.array([np.sum(g[r:] ** 2) for r in range(i + 1)])
+    expect = _sequential_ranks(g, tau)
+    say(f"superdiagonal {i}: exact ranks {expect}")
+    res = tucker.sthosvd(to_dev(torch.from_numpy(x)), eps, gram_precision="qr")
+    assert res.ranks == expect
+    lam = res.eigvals[0].cpu().numpy()
+    sig = np.sqrt(np.maximum(lam, 0))
+    assert np.all(np.abs(sig - g) <= 256 * i * U * g[0])
+    r1 = expect[0]
+    assert abs(res.discarded[0] - tails[r1]) <= 1e-3 * tails[r1] + 1e-300
+
+
+def test_qr_path_rejects_hooi_and_wide_modes():
+    x = to_dev(synth.random_tensor((8, 6, 5), seed=1))
+    with pytest.raises(tucker.TuckerError):
+        tucker.hooi(x, 0.1, gram_precision="qr")
+    with pytest.raises(tucker.TuckerError):
+        tucker.sthosvd(to_dev(synth.random_tensor((130, 4, 3), seed=2)), 0.1,
+                       gram_precision="qr")
