@@ -173,6 +173,56 @@ def kernel_rates(x, res, gp, tp, reps, stream):
             "ttm_gbs": round((b + zbytes) / tt / 1e9, 1)}
 
 
+def time_qr(x, mode, reps, stream):
+    """Average duration of one qr_r_mode_n call (its tree of tsqr launches)
+    on the library's stream, with HIP events on that stream."""
+    import ctypes
+    lib = tucker.library()
+    sh = tucker.shape_of(x)
+    need = lib.qr_workspace_bytes(ctypes.byref(sh), mode)
+    ws = tucker._workspace(need, x.device)
+    j = x.shape[mode]
+    r = tucker.empty_colmajor(j, j, x.device)
+    args = (ctypes.byref(sh), x.data_ptr(), mode, r.data_ptr(), None, tucker._aligned(ws), need,
+            ctypes.c_void_p(stream.cuda_stream))
+    tucker._check(lib.qr_r_mode_n(*args))
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(reps):
+            tucker._check(lib.qr_r_mode_n(*args))
+        end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps
+
+
+def qr_leg(x, w, steps, warmup, stream, eps=1e-5):
+    """The QR-preprocessed SVD path (Sec. IX) against the FP64 Gram path on
+    the same FP32-stored tensor at an eps where the Gram's squared singular
+    values approach their rounding level; plus the mode-1 tall-skinny QR
+    alone (Householder flops 2 m J^2 - 2 J^3 / 3, FP64 vector arithmetic)."""
+    import dataclasses
+    we = dataclasses.replace(w, eps=eps)
+    out = {"eps": eps, "storage": "float32", "ttm": "fp64"}
+    for name, gp in (("qr", "qr"), ("fp64_gram", "fp64")):
+        leg, _ = run_leg(f"qr-leg {name}", x, we, gp, "fp64", steps, warmup)
+        out[name] = leg
+    out["cost_ratio_qr_vs_gram"] = round(out["qr"]["ms_per_step"] /
+                                         out["fp64_gram"]["ms_per_step"], 3)
+    j = x.shape[0]
+    m = x.numel() // j
+    t = time_qr(x, 0, 3, stream)
+    fl = 2.0 * m * j * j - 2.0 * j ** 3 / 3.0
+    out["mode1_tsqr"] = {"ms": round(t * 1e3, 3), "tflops": round(fl / t / 1e12, 3),
+                         "frac_fp64_peak": round(fl / t / 1e12 / FP64_MFMA_PEAK_TFS, 4),
+                         "rows": m, "cols": j}
+    log(f"[qr] eps {eps}: qr {out['qr']['ms_per_step']} ms ranks {out['qr']['ranks']}, "
+        f"fp64 gram {out['fp64_gram']['ms_per_step']} ms ranks {out['fp64_gram']['ranks']}; "
+        f"mode-1 TSQR {t * 1e3:.2f} ms = {fl / t / 1e12:.2f} TFLOP/s")
+    return out
+
+
 def profile_kernels(w, dev, stream):
     """Launches for hardware-counter runs: 3x the mode-1 split Gram, 3x the
     mode-1 split TTM (R = 16) and 3x a plain copy of the same FP32 tensor,
@@ -416,6 +466,8 @@ def main():
                     help="skip the paper's 200^4 workload and its mode-order sweep")
     ap.add_argument("--no-c256", action="store_true",
                     help="skip the 68.7 GB combustion256 leg (mode orders 1..5 and 5..1)")
+    ap.add_argument("--no-qr", action="store_true",
+                    help="skip the QR-preprocessed SVD leg (Sec. IX) at eps 1e-5")
     ap.add_argument("--gram-reps", type=int, default=10)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="counter runs: only the mode-1 split Gram and TTM of the FP32 tensor "
@@ -455,6 +507,9 @@ def main():
                                       args.warmup)
         kern["mixed"] = kernel_rates(x32, resm, "split_bf16", "bf16x3", args.gram_reps, stream)
         log(f"[mixed] mode-1 kernels {kern['mixed']}")
+    qr_out = None
+    if x32 is not None and not args.no_qr:
+        qr_out = qr_leg(x32, w, max(1, args.steps // 2), 1, stream)
 
     head = "mixed" if "mixed" in legs else "fp64"
     x = x32 if head == "mixed" else x64
@@ -497,6 +552,8 @@ def main():
             "ranks_equal": legs["fp64"]["ranks"] == legs["mixed"]["ranks"],
             "relerr_fp64": legs["fp64"]["relerr"], "relerr_mixed": legs["mixed"]["relerr"],
             "abs_delta": abs(legs["fp64"]["relerr"] - legs["mixed"]["relerr"])}
+    if qr_out is not None:
+        out["qr_svd"] = qr_out
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(x, w.eps, head)

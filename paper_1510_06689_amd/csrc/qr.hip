@@ -39,61 +39,147 @@ __device__ __forceinline__ double qr_wave_sum(double v) {
     return v;
 }
 
-__device__ __forceinline__ double qr_lane_value(double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+// Cross-lane exchanges on VALU (no LDS round trip):
+//   offset 32: v_permlane32_swap(a, b) -> ([a 0-31, b 0-31], [a 32-63, b 32-63]),
+//   offset 16: v_permlane16_swap(a, b) -> (even rows of a, b; odd rows of a, b),
+// so first + second adds a value to its partner's (l ^ 32, resp. the other
+// row of the pair) with lanes below the offset holding a's pair sum and lanes
+// above it holding b's; offsets 8, 4, 2, 1 pair lanes inside a 16-lane row
+// with the DPP patterns row_ror:8, row_half_mirror, quad_perm [2,3,0,1] and
+// [1,0,3,2] (each an involution across that offset's bit).
+template <int OFF>
+__device__ __forceinline__ void pair_swap(double a, double b, double& x, double& y) {
+    const int al = __double2loint(a), ah = __double2hiint(a);
+    const int bl = __double2loint(b), bh = __double2hiint(b);
+    if constexpr (OFF == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+        x = __hiloint2double(hi[0], lo[0]);
+        y = __hiloint2double(hi[1], lo[1]);
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        x = __hiloint2double(hi[0], lo[0]);
+        y = __hiloint2double(hi[1], lo[1]);
+    }
+}
+
+template <int OFF>
+__device__ __forceinline__ double dpp_partner(double v) {
+    constexpr int ctrl = OFF == 8 ? 0x128 : OFF == 4 ? 0x141 : OFF == 2 ? 0x4e : 0xb1;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of CPW per-lane values at once: at offsets 32, 16, ...
-// each lane keeps half of its values (the upper half where its offset bit is
-// set) and adds its partner's copy of that half; after log2(CPW) stages the
-// remaining value is summed over the lanes that share those bits.  Lane l
-// returns the total for the column slot whose bits lane_of_slot<CPW> sets in
-// l (offset bit 32 >> s stands for CPW >> (s + 1)); all lanes of a group hold
-// bitwise the same total (every stage adds the same two operands).
-template <int CPW>
-__device__ __forceinline__ double reduce_scatter(double (&d)[CPW], int lane) {
-#pragma unroll
-    for (int s = 0; (CPW >> s) > 1; ++s) {
-        const int off = 32 >> s;
-        const int half = (CPW >> s) / 2;
-        const bool up = (lane & off) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            const double keep = up ? d[half + i] : d[i];
-            const double send = up ? d[i] : d[half + i];
-            d[i] = keep + __shfl_xor(send, off, 64);
-        }
+// One reduce-scatter stage at offset OFF: the lane keeps value a (its offset
+// bit clear) or b (set) and adds its partner's copy of the same one.
+template <int OFF>
+__device__ __forceinline__ double rs_stage(double a, double b, bool up) {
+    if constexpr (OFF >= 16) {
+        double x, y;
+        pair_swap<OFF>(a, b, x, y);
+        return x + y;
+    } else {
+        const double keep = up ? b : a, send = up ? a : b;
+        return keep + dpp_partner<OFF>(send);
     }
-    constexpr int lg = CPW >= 16 ? 4 : CPW >= 8 ? 3 : CPW >= 4 ? 2 : CPW >= 2 ? 1 : 0;
-    double t = d[0];
-#pragma unroll
-    for (int off = 32 >> lg; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    return t;
 }
 
-// A lane holding the total of column slot q after reduce_scatter<CPW>.
+// Full sum stage at offset OFF (every lane of the pair gets the same bits).
+template <int OFF>
+__device__ __forceinline__ double sum_stage(double v) {
+    if constexpr (OFF >= 16) {
+        double x, y;
+        pair_swap<OFF>(v, v, x, y);
+        return x + y;
+    } else {
+        return v + dpp_partner<OFF>(v);
+    }
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+    v = sum_stage<32>(v);
+    v = sum_stage<16>(v);
+    v = sum_stage<8>(v);
+    v = sum_stage<4>(v);
+    v = sum_stage<2>(v);
+    return sum_stage<1>(v);
+}
+
+// Sum over the 64 lanes of NS per-lane values at once (the slots OFFS ..
+// OFFS + NS - 1 of d): at offsets 32, 16, ... each lane keeps half of its
+// values (the upper half where its offset bit is set) and adds its partner's
+// copy of that half; after log2(NS) stages the remaining value is summed over
+// the lanes that share those bits.  Lane l returns the total for slot
+// OFFS + slot_of_lane<NS>(l) (offset bit 32 >> s stands for NS >> (s + 1));
+// all lanes of a group hold bitwise the same total (every stage adds the
+// same two operands).
+template <int NS, int CPW, int OFFS>
+__device__ __forceinline__ double reduce_window(double (&d)[CPW], int lane) {
+    constexpr int lg = NS >= 16 ? 4 : NS >= 8 ? 3 : NS >= 4 ? 2 : NS >= 2 ? 1 : 0;
+    static_assert((1 << lg) == NS && OFFS + NS <= CPW, "window of a power-of-two width");
+    if constexpr (lg >= 1) {
+#pragma unroll
+        for (int i = 0; i < NS / 2; ++i)
+            d[OFFS + i] = rs_stage<32>(d[OFFS + i], d[OFFS + NS / 2 + i], lane & 32);
+    }
+    if constexpr (lg >= 2) {
+#pragma unroll
+        for (int i = 0; i < NS / 4; ++i)
+            d[OFFS + i] = rs_stage<16>(d[OFFS + i], d[OFFS + NS / 4 + i], lane & 16);
+    }
+    if constexpr (lg >= 3) {
+#pragma unroll
+        for (int i = 0; i < NS / 8; ++i)
+            d[OFFS + i] = rs_stage<8>(d[OFFS + i], d[OFFS + NS / 8 + i], lane & 8);
+    }
+    if constexpr (lg >= 4) d[OFFS] = rs_stage<4>(d[OFFS], d[OFFS + 1], lane & 4);
+    double t = d[OFFS];
+    if constexpr (lg < 1) t = sum_stage<32>(t);
+    if constexpr (lg < 2) t = sum_stage<16>(t);
+    if constexpr (lg < 3) t = sum_stage<8>(t);
+    if constexpr (lg < 4) t = sum_stage<4>(t);
+    t = sum_stage<2>(t);
+    return sum_stage<1>(t);
+}
+
+// Window slot whose total lane l holds after reduce_window<CPW, ...>.
 template <int CPW>
-__device__ __forceinline__ constexpr int lane_of_slot(int q) {
-    int l = 0;
-    for (int s = 0; (CPW >> s) > 1; ++s)
-        if (q & (CPW >> (s + 1))) l |= 32 >> s;
-    return l;
-}
-
-// a[p][q0] for a wave-uniform runtime q0, as a masked sum (exact: the other
-// terms are zero).  A select chain here gets folded into a dynamically
-// indexed load, which would move the whole tile array to scratch memory.
-template <int RPL, int CPW>
-__device__ __forceinline__ double slot_value(const double (&a)[RPL][CPW], int p, int q0) {
-    double x = 0.0;
+__device__ __forceinline__ int slot_of_lane(int l) {
+    int q = 0;
 #pragma unroll
-    for (int q = 0; q < CPW; ++q) x = fma(q == q0 ? 1.0 : 0.0, a[p][q], x);
-    return x;
+    for (int s = 0; (CPW >> s) > 1; ++s)
+        if (l & (32 >> s)) q += CPW >> (s + 1);
+    return q;
 }
 
 }  // namespace
+
+// Householder reflector of the stacked column [R_kk; col] (dlarfg convention:
+// beta = -sign(alpha) ||.||, tau = (beta - alpha) / beta, v = col / (alpha -
+// beta), no reflection when col is zero).  Called by the one wave owning
+// column k; writes v (BR values) and tau to vbuf and beta to R_kk.
+template <int RPL, int BR, int JC>
+__device__ __forceinline__ void make_reflector(const double (&col)[RPL], int k, double* Rs,
+                                               double* vbuf, int lane) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) s = fma(col[p], col[p], s);
+    const double xn2 = wave_total(s);
+    const double alpha = Rs[k * JC + k];
+    double tau = 0.0, scal = 0.0;
+    if (xn2 > 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, xn2));
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+        if (lane == 0) Rs[k * JC + k] = beta;
+    }
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) vbuf[lane + 64 * p] = col[p] * scal;
+    if (lane == 0) vbuf[BR] = tau;
+}
 
 // Rows of A: row r = b * L + l holds the elements (r, j) at b * sB + j * sJ + l.
 struct QrSrc {
@@ -109,8 +195,102 @@ struct QrGeom {
     static constexpr int RPL = 64 / CPW;       // tile rows per lane (64 doubles per lane)
     static constexpr int BR = 64 * RPL;   // tile rows
     static constexpr int VB = BR + 2;     // v buffer pitch (v, then tau)
-    static constexpr size_t lds_bytes = ((size_t)JC * JC + 2 * VB + kQrWaves) * sizeof(double);
+    static constexpr size_t lds_bytes =
+        ((size_t)JC * JC + 2 * VB + kQrWaves + kQrWaves * CPW) * sizeof(double);
 };
+
+// Steps k = 8 KB .. 8 KB + 7 of the reduction of [R; tile] (kQrWaves = 8
+// columns, one per wave, all in slot KB).  Slots q < KB hold finished
+// columns, slots q > KB only columns c > k, and slot KB column k itself in
+// wave kk = k - 8 KB (the owner, which forms reflector k) and live columns in
+// waves above it; the live slots lie in the window of the last NS slots,
+// whose width shrinks block by block.  Reflector k is published in
+// vb[k & 1] behind one barrier per column: that buffer is rewritten two
+// columns later, after every wave has passed the next barrier (and so
+// finished this step).  R row k, column c is read and written only by the
+// wave owning c.
+template <int JC, int KB>
+__device__ __forceinline__ void absorb_block(double (&a)[QrGeom<JC>::RPL][QrGeom<JC>::CPW],
+                                             int J, int wave, int lane, double* Rs,
+                                             double* vb, double* wb) {
+    using G = QrGeom<JC>;
+    constexpr int CPW = G::CPW, RPL = G::RPL, BR = G::BR, VB = G::VB;
+    constexpr int LIVE = CPW - KB;
+    constexpr int NS = LIVE > 8 ? 16 : LIVE > 4 ? 8 : LIVE > 2 ? 4 : LIVE > 1 ? 2 : 1;
+    constexpr int OFFS = CPW - NS;
+    for (int kk = 0; kk < kQrWaves; ++kk) {
+        const int k = KB * kQrWaves + kk;
+        if (k >= J) return;  // uniform
+        double* vk = vb + (k & 1) * VB;
+        if (wave == kk) {
+            double col[RPL];
+#pragma unroll
+            for (int p = 0; p < RPL; ++p) col[p] = a[p][KB];
+            make_reflector<RPL, BR, JC>(col, k, Rs, vk, lane);
+        }
+        __syncthreads();
+        // tau = 0 (identity reflector) leaves v = 0 and w = 0: the update
+        // below is then exact no-op arithmetic, so the step needs no branch
+        const double tau = vk[BR];
+        double v[RPL];
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) v[p] = vk[lane + 64 * p];
+        // this lane's window slot after the reduction, and its R_kc (read
+        // now, used after the reduction)
+        const int ql = OFFS + slot_of_lane<NS>(lane);
+        const int cl = wave + kQrWaves * ql;
+        const bool act = cl > k && cl < J;
+        const double rk = act ? Rs[k * JC + cl] : 0.0;
+        double d[CPW];
+#pragma unroll
+        for (int q = OFFS; q < CPW; ++q) {
+            double s = 0.0;
+            const int c = wave + kQrWaves * q;
+            if (q >= KB && (q > KB || wave > kk) && c < J) {  // uniform
+#pragma unroll
+                for (int p = 0; p < RPL; ++p) s = fma(v[p], a[p][q], s);
+            }
+            d[q] = s;
+        }
+        const double tot = reduce_window<NS, CPW, OFFS>(d, lane);
+        {
+            const double w = act ? tau * (rk + tot) : 0.0;
+            if (act) Rs[k * JC + cl] = rk - w;  // all lanes of the slot: same value
+            wb[ql] = w;
+        }
+        // LDS operations of one wave complete in order: the reads below see
+        // this wave's writes above (the wave barrier keeps the compiler from
+        // moving them across)
+        __builtin_amdgcn_wave_barrier();
+        double wq[CPW];
+        if constexpr (NS >= 2) {
+#pragma unroll
+            for (int q = OFFS; q < CPW; q += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(wb + q);
+                wq[q] = t.x;
+                wq[q + 1] = t.y;
+            }
+        } else {
+            wq[OFFS] = wb[OFFS];
+        }
+#pragma unroll
+        for (int q = KB; q < CPW; ++q) {
+            const int c = wave + kQrWaves * q;
+            if ((q > KB || wave > kk) && c < J) {  // uniform
+#pragma unroll
+                for (int p = 0; p < RPL; ++p) a[p][q] = fma(-v[p], wq[q], a[p][q]);
+            }
+        }
+    }
+}
+
+template <int JC, int KB>
+__device__ __forceinline__ void absorb_from(double (&a)[QrGeom<JC>::RPL][QrGeom<JC>::CPW], int J,
+                                            int wave, int lane, double* Rs, double* vb,
+                                            double* wb) {
+    absorb_block<JC, KB>(a, J, wave, lane, Rs, vb, wb);
+    if constexpr (KB + 1 < QrGeom<JC>::CPW) absorb_from<JC, KB + 1>(a, J, wave, lane, Rs, vb, wb);
+}
 
 // One level of the reduction.  Workgroup g absorbs rows
 // [g * rows_per_wg, min(rows, (g + 1) * rows_per_wg)) of src.  Unless r_final
@@ -133,9 +313,11 @@ __global__ __launch_bounds__(kQrThreads) void tsqr_kernel(QrSrc src, int J, int6
     double* Rs = smem;              // JC x JC, row-major
     double* vb = Rs + JC * JC;      // 2 x VB
     double* red = vb + 2 * VB;      // kQrWaves
+    double* wbuf = red + kQrWaves;  // kQrWaves x CPW: one wave's w values per step
     // wave index made visibly uniform: column offsets and tests stay scalar
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double* wb = wbuf + wave * CPW;
 
     for (int i = tid; i < JC * JC; i += kQrThreads) Rs[i] = 0.0;
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
@@ -167,66 +349,13 @@ __global__ __launch_bounds__(kQrThreads) void tsqr_kernel(QrSrc src, int J, int6
                 ss = fma(x, x, ss);
             }
         }
-        // ---- reduce [R; tile] column by column
-        for (int k = 0; k < J; ++k) {
-            double* vk = vb + (k & 1) * VB;
-            if (wave == k % kQrWaves) {
-                const int q0 = k / kQrWaves;
-                double s = 0.0;
-#pragma unroll
-                for (int p = 0; p < RPL; ++p) {
-                    const double x = slot_value(a, p, q0);
-                    s = fma(x, x, s);
-                }
-                const double xn2 = qr_wave_sum(s);
-                const double alpha = Rs[k * JC + k];
-                double tau = 0.0, scal = 0.0;
-                if (xn2 > 0.0) {  // otherwise the reflector is the identity
-                    const double nrm = sqrt(fma(alpha, alpha, xn2));
-                    const double beta = alpha >= 0.0 ? -nrm : nrm;
-                    tau = (beta - alpha) / beta;
-                    scal = 1.0 / (alpha - beta);
-                    if (lane == 0) Rs[k * JC + k] = beta;
-                }
-#pragma unroll
-                for (int p = 0; p < RPL; ++p) vk[lane + 64 * p] = slot_value(a, p, q0) * scal;
-                if (lane == 0) vk[BR] = tau;
-            }
-            // one barrier per column: vk is rewritten two columns later, after
-            // every wave has passed the next barrier (and so finished this step)
-            __syncthreads();
-            // tau = 0 (identity reflector) leaves v = 0 and w = 0: the update
-            // below is then exact no-op arithmetic, so the step needs no branch
-            const double tau = vk[BR];
-            double v[RPL];
-#pragma unroll
-            for (int p = 0; p < RPL; ++p) v[p] = vk[lane + 64 * p];
-            double d[CPW];
-#pragma unroll
-            for (int q = 0; q < CPW; ++q) {
-                const int c = wave + kQrWaves * q;
-                double s = 0.0;
-                if (c > k && c < J) {
-#pragma unroll
-                    for (int p = 0; p < RPL; ++p) s = fma(v[p], a[p][q], s);
-                }
-                d[q] = s;
-            }
-            const double tot = reduce_scatter<CPW>(d, lane);
-#pragma unroll
-            for (int q = 0; q < CPW; ++q) {
-                const int c = wave + kQrWaves * q;
-                if (c > k && c < J) {  // R row k, column c: read and written by this wave only
-                    const double rk = Rs[k * JC + c];
-                    const double w = tau * (rk + qr_lane_value(tot, lane_of_slot<CPW>(q)));
-#pragma unroll
-                    for (int p = 0; p < RPL; ++p) a[p][q] = fma(-v[p], w, a[p][q]);
-                    if (lane == 0) Rs[k * JC + c] = rk - w;
-                }
-            }
-        }
+        // ---- reduce [R; tile] column by column.  Every wave has finished the
+        // previous tile's last step (which may read vb[0]) before reflector 0
+        // of this tile is written there.
+        __syncthreads();
+        absorb_from<JC, 0>(a, J, wave, lane, Rs, vb, wb);
     }
-    ss = qr_wave_sum(ss);
+    ss = wave_total(ss);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
     if (!r_final) {
