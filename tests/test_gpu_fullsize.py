@@ -112,3 +112,47 @@ def test_fullsize_sthosvd_fp64_and_mixed(tensors):
     relm = _check_invariants(x32, rm, W.eps, 1e-6, 1e-6)
     say(f"relerr fp64 {rel64:.6e} mixed {relm:.6e}")
     assert abs(relm - rel64) <= 1e-4
+
+
+def test_fullsize_mode1_qr_r_gram_identity(tensors):
+    # R of the 2^24 x 128 mode-1 unfolding (FP32 storage, the QR leg's input):
+    # (R^T R)_ij equals the Gram entry S_ij up to Householder's columnwise
+    # backward error, |d(R^T R)_ij| <= 2 gamma ||a_i|| ||a_j||
+    x = tensors[1]
+    r, sumsq = tucker.qr_r(x, 0)
+    torch.cuda.synchronize()
+    r = r.cpu().numpy()
+    assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) >= 0)
+    rtr = r.T @ r
+    gamma = 4096 * U64
+    for i, j in PAIRS:
+        sub = mode1_rows(x, i, j)
+        ref = oracle.gram(sub, 0)
+        d = np.sqrt(np.diag(ref))
+        got = np.array([[rtr[i, i], rtr[i, j]], [rtr[j, i], rtr[j, j]]])
+        tol = 2 * gamma * np.outer(d, d) + 64 * U64 * np.outer(d, d)
+        say(f"qr (R^T R)[{i},{j}] = {got[0, 1]:.12e} oracle {ref[0, 1]:.12e}")
+        assert np.all(np.abs(got - ref) <= tol), (i, j, got - ref, tol)
+    nu = float(np.trace(rtr))
+    assert math.isclose(float(sumsq), nu, rel_tol=1e-12)
+
+
+def test_fullsize_qr_path_eps_1e5(tensors):
+    # the bench's QR leg: eps = 1e-5 on the FP32-stored tensor, QR path and
+    # FP64 Gram path; ranks equal, ST-HOSVD identities on both
+    x32 = tensors[1]
+    eps = 1e-5
+    rq = tucker.sthosvd(x32, eps, gram_precision="qr")
+    rg = tucker.sthosvd(x32, eps, gram_precision="fp64")
+    say(f"eps 1e-5 ranks qr {rq.ranks} fp64 gram {rg.ranks}")
+    assert rq.ranks == rg.ranks
+    # FP32 storage of the intermediate tensors bounds the identities at ~u32
+    relq = _check_invariants(x32, rq, eps, 1e-6, 1e-9)
+    relg = _check_invariants(x32, rg, eps, 1e-6, 1e-9)
+    say(f"relerr qr {relq:.6e} fp64 gram {relg:.6e}")
+    assert abs(relq - relg) <= 1e-3 * eps
+    # the leading singular values agree (sigma from QR vs sqrt of the Gram's eigenvalues)
+    sq = np.sqrt(np.maximum(rq.eigvals[0].cpu().numpy(), 0))
+    sg = np.sqrt(np.maximum(rg.eigvals[0].cpu().numpy(), 0))
+    s1 = math.sqrt(rq.norm2)
+    assert np.abs(sq[:20] - sg[:20]).max() <= 1e-9 * s1
