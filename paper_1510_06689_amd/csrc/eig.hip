@@ -714,6 +714,16 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     __syncthreads();
 
     // ---- 5. back-transformation X <- Q X, Q = H_0 H_1 ... H_{J-3} -------
+    // With A in registers (J <= JP) the LDS region, free again after the
+    // inverse iteration, holds all reflectors: copy them back in one
+    // coalesced pass so that the loop below reads LDS instead of issuing a
+    // dependent global load per reflector.
+    const double* Hb = H;
+    if constexpr (JP > 0) {
+        for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) reg[idx] = H[idx];
+        __syncthreads();
+        Hb = reg;
+    }
     for (int j = wave; j < R; j += kEigWaves) {
         double xr[kMaxVecSlots];
 #pragma unroll
@@ -729,7 +739,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
 #pragma unroll
             for (int q = 0; q < kMaxVecSlots; ++q) {
                 const int t = lane + 64 * q;
-                hv[q] = (q < nslot && t > k && t < J) ? H[(size_t)k * J + (t - k - 1)] : 0.0;
+                hv[q] = (q < nslot && t > k && t < J) ? Hb[(size_t)k * J + (t - k - 1)] : 0.0;
                 s += hv[q] * xr[q];
             }
             s = b * wave_sum(s);
