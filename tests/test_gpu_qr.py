@@ -163,3 +163,42 @@ def test_qr_path_rejects_hooi_and_wide_modes():
     with pytest.raises(tucker.TuckerError):
         tucker.sthosvd(to_dev(synth.random_tensor((130, 4, 3), seed=2)), 0.1,
                        gram_precision="qr")
+
+
+def test_qr_path_rank_deficient_fixed_ranks():
+    # mode 1 has 12 rows for 50 columns: R has rank <= 12, so 8 of the 20
+    # requested singular vectors belong to zero singular values, where the
+    # top half of the Jordan-Wielandt eigenvector can vanish; the factor must
+    # still be orthonormal and the reconstruction exact
+    x = synth.random_tensor((50, 3, 4), seed=21)
+    xh = x.numpy()
+    res = tucker.sthosvd(to_dev(x), 0.0, ranks=(20, 3, 4), gram_precision="qr")
+    assert res.ranks == (20, 3, 4)
+    u = res.factors[0].cpu().numpy()
+    assert np.abs(u.T @ u - np.eye(20)).max() <= 1e-12
+    sig = np.sqrt(np.maximum(res.eigvals[0].cpu().numpy(), 0))
+    ref = np.linalg.svd(np_unfold(xh, 0), compute_uv=False)
+    s1 = ref[0]
+    assert np.abs(sig[:12] - ref[:12]).max() <= 64 * 50 * U * s1
+    assert np.all(sig[12:] <= 64 * 50 * U * s1)
+    xr = tucker.reconstruct(res.core, res.factors).cpu().numpy()
+    assert np.abs(xr - xh).max() <= 1e-12 * np.abs(xh).max()
+
+
+def test_qr_path_zero_tensor():
+    x = torch.zeros((6, 5, 4), dtype=torch.float64)
+    res = tucker.sthosvd(to_dev(x), 1e-3, gram_precision="qr")
+    assert res.ranks == (1, 1, 1)
+    assert res.norm2 == 0.0
+    for u in res.factors:
+        u = u.cpu().numpy()
+        assert np.all(np.isfinite(u))
+        assert abs(float((u.T @ u)[0, 0]) - 1.0) <= 1e-14
+    assert np.all(res.core.cpu().numpy() == 0.0)
+
+
+def test_qr_r_is_deterministic():
+    x = to_dev(synth.random_tensor((64, 33, 40), seed=4))
+    a, _ = tucker.qr_r(x, 1)
+    b, _ = tucker.qr_r(x, 1)
+    assert torch.equal(a, b)
