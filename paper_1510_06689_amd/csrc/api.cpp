@@ -400,14 +400,13 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     for (int s = 0; s < N; ++s) {
         const int n = pl.order[s];
         ModeView v = mode_view(cur, N, n);
-        // A narrow mode (J <= 32) over a small unfolding takes the FP64 Gram
-        // even on the mixed path: at J <= 32 its arithmetic intensity on FP32
-        // data, (J + 1) / 4 flop/B, is below the FP64 MFMA ridge, so it costs
-        // no more than the split one, and it needs no guard recomputation.
+        // A narrow mode (J <= 32) over a small unfolding, or one the narrow
+        // FP64 kernel streams, takes the FP64 Gram even on the mixed path: at
+        // J <= 32 its arithmetic intensity on FP32 data, (J + 1) / 4 flop/B,
+        // is below the FP64 MFMA ridge, so it costs no more than the split
+        // one, and it needs no guard recomputation.
         int gprec = opt->gram_precision;
-        if (gprec == TK_GRAM_SPLIT_BF16 && v.J <= 32 &&
-            (double)v.L * (double)v.J * (double)v.B <= kSmallFp64GramElems)
-            gprec = TK_GRAM_FP64;
+        if (gprec == TK_GRAM_SPLIT_BF16 && mixed_takes_fp64_gram(v)) gprec = TK_GRAM_FP64;
         if (qr) {
             // R of Y_(n)^T, then the Jordan-Wielandt matrix [[0, R^T], [R, 0]]
             TK_TRY(launch_tsqr(ycur, x->dtype, v, plan_qr(v), qr_ws, r_ws,

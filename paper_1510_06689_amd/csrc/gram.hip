@@ -196,6 +196,118 @@ __global__ void gram_trace(const double* __restrict__ s, int J, double* __restri
     }
 }
 
+// ------------------------------------------------------------ narrow modes
+//
+// J <= 32 where every unfolding row is made of long contiguous runs (L a
+// multiple of 8): no LDS tile.  A step is 32 consecutive l of one slab b.
+// Lane t of a wave owns unfolding row t % 16 (and 16 + t % 16 when J > 16)
+// and the eight columns l0 + 8 (t / 16) + e of a step, read with one vector
+// load per row straight from HBM.  For MFMA call e each lane's element is
+// both A[t % 16][t / 16] and B[t / 16][t % 16], so the eight calls sum
+// y_i y_j over the step's 32 columns.  A wave takes U consecutive steps at a
+// time (one contiguous run of 32 U elements per row); its accumulators stay
+// in registers until the end, where the 8 waves of a workgroup fold them
+// through LDS, in a fixed order, into one partial per workgroup.
+constexpr int kNarrowThreads = 512;
+constexpr int kNarrowWaves = kNarrowThreads / 64;
+
+template <typename T>
+struct Run8;
+template <>
+struct Run8<float> {
+    typedef float type __attribute__((ext_vector_type(8)));
+};
+template <>
+struct Run8<double> {
+    typedef double type __attribute__((ext_vector_type(8)));
+};
+
+// Block pairs of the narrow kernel: (0,0) for J <= 16; (0,0), (0,1), (1,1)
+// (pair_of order with nb = 2) for 16 < J <= 32.
+template <int JN>
+constexpr int kNarrowPairs = JN == 16 ? 1 : 3;
+
+template <typename T, int JN, int U>
+__global__ __launch_bounds__(kNarrowThreads) void gram_narrow_f64(
+    const T* __restrict__ y, int64_t L, int J, int64_t nsteps, int P,
+    double* __restrict__ partial) {
+    constexpr int NR = JN / 16;  // row blocks per lane
+    constexpr int NP = kNarrowPairs<JN>;
+    constexpr int NA = JN == 16 ? 2 : 3;  // J <= 16: two accumulator chains
+    typedef typename Run8<T>::type run_t;
+    __shared__ double red[kNarrowWaves * NP * 256];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int p = blockIdx.x;
+    const int64_t s0 = nsteps * p / P, s1 = nsteps * (p + 1) / P;
+    const int64_t sb = (L + 31) >> 5;  // steps per slab
+    const int64_t slab = (int64_t)J * L;
+    int64_t roff[NR];
+    bool rok[NR];
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+        const int r = 16 * h + r16;
+        rok[h] = r < J;
+        roff[h] = (int64_t)(rok[h] ? r : 0) * L + 8 * k4;
+    }
+    d4_t acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t q = s0 + (int64_t)wave * U; q < s1; q += (int64_t)kNarrowWaves * U) {
+        int64_t b = q / sb;
+        int64_t l0 = (q - b * sb) << 5;
+        run_t v[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = q + u < s1 && l0 + 8 * k4 < L;
+            const T* base = y + b * slab + l0;
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+                if (ok && rok[h])
+                    v[u][h] = *reinterpret_cast<const run_t*>(base + roff[h]);
+                else
+                    v[u][h] = run_t(0);
+            }
+            l0 += 32;
+            if (l0 >= L) {
+                l0 = 0;
+                ++b;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const double a0 = (double)v[u][0][e];
+                if constexpr (JN == 16) {
+                    acc[e & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[e & 1], 0, 0, 0);
+                } else {
+                    const double a1 = (double)v[u][1][e];
+                    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[2], 0, 0, 0);
+                }
+            }
+    }
+    if constexpr (JN == 16) acc[0] += acc[1];
+
+    // D[row][col] of pair c sits in lane col + 16 (row % 4), register row / 4
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[(wave * NP + c) * 256 + (4 * r + k4) * 16 + r16] = acc[c][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NP * 256; e += kNarrowThreads) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kNarrowWaves; ++w) s += red[w * NP * 256 + e];
+        partial[(int64_t)p * NP * 256 + e] = s;
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 static int round_jb(int J) {
@@ -229,9 +341,30 @@ static GramShape gram_shape_rt(int jb) {
     }
 }
 
-GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
-    (void)elem_bytes;
-    if (precision == TK_GRAM_SPLIT_BF16) return plan_gram_mixed(v);
+// Narrow-mode plan: one partial per workgroup, at most 2 per CU, each
+// workgroup holding at least one batch of steps per wave.
+constexpr int kNarrowStepsF32 = 4, kNarrowStepsF64 = 2;  // U: steps per batch
+
+static int64_t narrow_steps(const ModeView& v) { return v.B * ((v.L + 31) / 32); }
+
+static GramPlan plan_narrow(const ModeView& v, int elem_bytes) {
+    GramPlan pl{};
+    pl.narrow = v.J <= 16 ? 16 : 32;
+    pl.nb = pl.narrow / 16;
+    pl.npairs = pl.nb * (pl.nb + 1) / 2;
+    pl.G = 1;
+    pl.pairs_per_group = pl.npairs;
+    const int U = elem_bytes == 8 ? kNarrowStepsF64 : kNarrowStepsF32;
+    const int64_t per_wg = (int64_t)kNarrowWaves * U;
+    const int64_t cap = 2 * (int64_t)device_cu_count();
+    int64_t P = (narrow_steps(v) + per_wg - 1) / per_wg;
+    pl.P = (int)(P < 1 ? 1 : P > cap ? cap : P);
+    pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
+    pl.partial_bound = (size_t)cap * pl.npairs * 256 * sizeof(double);
+    return pl;
+}
+
+static GramPlan plan_tiled(const ModeView& v) {
     GramPlan pl{};
     GramShape gs = gram_shape_rt(round_jb(v.J));
     pl.KT = gs.KT;
@@ -245,6 +378,36 @@ GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
     pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
     pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
     return pl;
+}
+
+// The narrow kernel's plan where the view qualifies; its workspace bounds
+// also cover the tiled plan, which runs instead when the data pointer is not
+// aligned for the kernel's vector loads.
+GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes) {
+    if (precision == TK_GRAM_SPLIT_BF16) return plan_gram_mixed(v);
+    GramPlan tiled = plan_tiled(v);
+    if (!gram_narrow_view(v)) return tiled;
+    GramPlan pl = plan_narrow(v, elem_bytes);
+    if (tiled.partial_bytes > pl.partial_bytes) pl.partial_bytes = tiled.partial_bytes;
+    if (tiled.partial_bound > pl.partial_bound) pl.partial_bound = tiled.partial_bound;
+    return pl;
+}
+
+template <typename T, int JN>
+static int launch_narrow(const T* y, const ModeView& v, const GramPlan& pl, double* partial,
+                         hipStream_t st) {
+    constexpr int U = sizeof(T) == 8 ? kNarrowStepsF64 : kNarrowStepsF32;
+    hipLaunchKernelGGL((gram_narrow_f64<T, JN, U>), dim3(pl.P), dim3(kNarrowThreads), 0, st, y,
+                       v.L, v.J, narrow_steps(v), pl.P, partial);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+template <typename T>
+static int dispatch_narrow(const T* y, const ModeView& v, const GramPlan& pl, double* partial,
+                           hipStream_t st) {
+    return pl.narrow == 16 ? launch_narrow<T, 16>(y, v, pl, partial, st)
+                           : launch_narrow<T, 32>(y, v, pl, partial, st);
 }
 
 template <typename T, int JB>
@@ -416,8 +579,15 @@ int launch_gram(const void* y, int dtype, const ModeView& v, int precision, doub
     if (ws_bytes < pl.partial_bytes)
         return fail(TK_ERR_WORKSPACE, "gram workspace %zu < %zu", ws_bytes, pl.partial_bytes);
     double* partial = (double*)ws;
+    // the narrow kernel's 8-element vector loads need the run's own alignment
+    if (pl.narrow && (uintptr_t)y % (8 * dtype_size(dtype)) != 0) pl = plan_tiled(v);
     if (precision == TK_GRAM_SPLIT_BF16) {
         TK_TRY(launch_gram_mixed((const float*)y, v, pl, partial, st));
+    } else if (pl.narrow) {
+        if (dtype == TK_F64)
+            TK_TRY(dispatch_narrow((const double*)y, v, pl, partial, st));
+        else
+            TK_TRY(dispatch_narrow((const float*)y, v, pl, partial, st));
     } else if (dtype == TK_F64) {
         TK_TRY(dispatch_partial((const double*)y, v, pl, partial, st));
     } else {

@@ -26,9 +26,7 @@ int64_t cap_rank(const tk_shape* x, const tk_options* opt, int n) {
 // modes take the FP64 Gram on the mixed path.
 int gram_prec(const tk_options* opt, const ModeView& v) {
     int g = opt->gram_precision;
-    if (g == TK_GRAM_SPLIT_BF16 && v.J <= 32 &&
-        (double)v.L * (double)v.J * (double)v.B <= kSmallFp64GramElems)
-        g = TK_GRAM_FP64;
+    if (g == TK_GRAM_SPLIT_BF16 && mixed_takes_fp64_gram(v)) g = TK_GRAM_FP64;
     return g;
 }
 

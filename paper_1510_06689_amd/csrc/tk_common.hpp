@@ -145,9 +145,16 @@ struct Carver {
 
 struct GramPlan {
     int KT, P, G, npairs, pairs_per_group, nb;
+    int narrow;            // 16 or 32: the FP64 narrow-mode kernel's row extent; 0: tiled
     size_t partial_bytes;  // this shape's partials
     size_t partial_bound;  // partials of any shape with this mode extent (grid cap)
 };
+// FP64 Gram without an LDS tile: J <= 32 where the unfolding rows are made
+// of long contiguous runs (L a multiple of 8, at least kNarrowMinRun).
+constexpr int64_t kNarrowMinRun = 64;
+inline bool gram_narrow_view(const ModeView& v) {
+    return v.J <= 32 && v.L % 8 == 0 && v.L >= kNarrowMinRun;
+}
 GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes);
 GramPlan plan_gram_mixed(const ModeView& v);
 int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
@@ -210,8 +217,13 @@ constexpr double kSplitGramGuard = 8.0 / 1073741824.0;
 // eps^2 / N = 8 * 2^-34 the threshold would feel it, so the TTMs run in FP64.
 constexpr double kSplitTtmFloor = 8.0 / 17179869184.0;
 // Mixed path: modes with J <= 32 and at most this many unfolding elements
-// use the FP64 Gram (2^26: 256 MB of FP32).
+// use the FP64 Gram (2^26: 256 MB of FP32), and so does any mode the FP64
+// narrow-mode kernel takes.
 constexpr double kSmallFp64GramElems = 67108864.0;
+inline bool mixed_takes_fp64_gram(const ModeView& v) {
+    return v.J <= 32 && ((double)v.L * (double)v.J * (double)v.B <= kSmallFp64GramElems ||
+                         gram_narrow_view(v));
+}
 size_t eig_scratch_doubles(int J);
 int launch_eig(const EigArgs& a, hipStream_t st);
 size_t eig_lds_bytes(int J);

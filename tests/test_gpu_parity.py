@@ -53,6 +53,50 @@ def test_gram_matches_oracle(dims, modes, dtype):
         assert math.isclose(float(sumsq.item()), nu, rel_tol=(xh.size + 2) * U64)
 
 
+# Narrow modes (J <= 32) whose unfolding rows are runs of L contiguous
+# elements, L a multiple of 8: the FP64 Gram streams them without an LDS
+# tile.  Runs that are whole 32-column steps and ragged ones, one and several
+# slabs (including slabs that change inside one wave's batch of steps),
+# J = 1, J < 16, J = 16, 16 < J < 32, J = 32, a workgroup count at the grid
+# cap with several batches per wave; offset = 1 shifts the data pointer by
+# one element, so the vector loads' alignment fails and the tiled kernel
+# runs instead.
+NARROW_CASES = [
+    ((96, 20, 7), 1),
+    ((200, 16, 3), 1),
+    ((72, 1, 5), 1),
+    ((64, 32, 2), 1),
+    ((8, 8, 5, 9), 2),
+    ((1 << 21, 16), 1),
+    ((1 << 20, 3, 11), 1),
+    ((4096, 30), 1),
+]
+
+
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dims,n", NARROW_CASES)
+def test_gram_narrow_modes(dims, n, dtype, offset):
+    say(f"narrow gram dims={dims} mode={n} dtype={dtype} offset={offset}")
+    x = synth.random_tensor(dims, seed=sum(dims) + n, dtype=dtype)
+    xh = x.double().numpy()
+    size = xh.size
+    buf = torch.empty(size + offset, dtype=dtype, device="cuda:0")
+    xd = buf[offset:].view(tuple(reversed(dims))).permute(*reversed(range(len(dims))))
+    xd.copy_(to_dev(x))
+    assert xd.data_ptr() % 64 == (0 if offset == 0 else x.element_size())
+    s, sumsq = tucker.gram(xd, n)
+    torch.cuda.synchronize()
+    s = s.cpu().numpy()
+    ref = oracle.gram(xh, n)
+    err = np.abs(s - ref)
+    tol = gram_tolerance(ref, size // dims[n])
+    assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
+    assert np.array_equal(s, s.T)
+    nu = oracle.norm2(xh)
+    assert math.isclose(float(sumsq.item()), nu, rel_tol=(size + 2) * U64)
+
+
 def test_gram_is_deterministic():
     x = to_dev(synth.random_tensor((96, 40, 50), seed=5))
     for n in range(3):
