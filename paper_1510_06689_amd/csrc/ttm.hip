@@ -109,6 +109,131 @@ __global__ __launch_bounds__(kTtmThreads) void ttm_f64_kernel(
     }
 }
 
+// ------------------------------------------------------------ narrow modes
+//
+// J <= 32 and K <= 16 where the rows of Y_(n) and Z_(n) are made of runs of
+// L contiguous elements (L a multiple of 8): no LDS.  A step is 16 E
+// consecutive l of one slab b (E = 16 bytes / element size).  In k-step s
+// lane t holds A[t % 16][4 s + t / 16] (op(M), FP64, loaded once) and reads
+// Y[4 s + t / 16][l0 + E (t % 16) + e], e < E, with one 16-byte load.  MFMA
+// call (s, e) takes that element as B[t / 16][t % 16], so accumulator e
+// gathers Z[r][l0 + E c + e] for output row r and column block c: each lane
+// ends up with E consecutive l of four output rows and stores them with one
+// 16-byte store per row.  Arithmetic is FP64 (exact products of the stored
+// values), rounded once to the storage type.
+constexpr int kNarrowTtmThreads = 512;
+constexpr int kNarrowTtmWaves = kNarrowTtmThreads / 64;
+
+template <typename T, int JN, int U>
+__global__ __launch_bounds__(kNarrowTtmThreads) void ttm_narrow_f64(
+    const T* __restrict__ y, int64_t L, int J, const double* __restrict__ m, int64_t ldm, int K,
+    int transpose, int64_t nsteps, int P, T* __restrict__ z) {
+    constexpr int E = 16 / (int)sizeof(T);  // columns per lane per load
+    constexpr int SC = 16 * E;              // columns per step
+    constexpr int NS = JN / 4;              // k-steps
+    typedef T vec_t __attribute__((ext_vector_type(E)));
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c16 = lane & 15, q4 = lane >> 4;
+
+    double a[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = 4 * s + q4;
+        a[s] = (c16 < K && i < J) ? (transpose ? m[i + ldm * c16] : m[c16 + ldm * i]) : 0.0;
+    }
+    bool iok[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) iok[s] = 4 * s + q4 < J;
+    bool rok[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rok[v] = 4 * v + q4 < K;
+
+    const int p = blockIdx.x;
+    const int64_t s0 = nsteps * p / P, s1 = nsteps * (p + 1) / P;
+    const int64_t sb = (L + SC - 1) / SC;  // steps per slab
+    const int64_t yslab = (int64_t)J * L, zslab = (int64_t)K * L;
+    for (int64_t q = s0 + (int64_t)wave * U; q < s1; q += (int64_t)kNarrowTtmWaves * U) {
+        int64_t b = q / sb;
+        int64_t l0 = (q - b * sb) * SC;
+        vec_t v[U][NS];
+        int64_t lo[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            lo[u] = b * zslab + l0 + E * c16;
+            ok[u] = q + u < s1 && l0 + E * c16 < L;
+            const T* src = y + b * yslab + l0 + E * c16;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (ok[u] && iok[s])
+                    v[u][s] = *reinterpret_cast<const vec_t*>(src + (int64_t)(4 * s + q4) * L);
+                else
+                    v[u][s] = vec_t(0);
+            }
+            l0 += SC;
+            if (l0 >= L) {
+                l0 = 0;
+                ++b;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            d4_t acc[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], (double)v[u][s][e],
+                                                                  acc[e], 0, 0, 0);
+            // D[row][col] sits in lane col + 16 (row % 4), register row / 4:
+            // this lane holds rows 4 w + q4, columns l0 + E c16 + e
+            if (ok[u]) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if (!rok[w]) continue;
+                    vec_t out;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) out[e] = (T)acc[e][w];
+                    *reinterpret_cast<vec_t*>(z + lo[u] + (int64_t)(4 * w + q4) * L) = out;
+                }
+            }
+        }
+    }
+}
+
+constexpr int kNarrowTtmStepsF32 = 2, kNarrowTtmStepsF64 = 2;  // U: steps per batch
+
+// Views the narrow TTM takes (the data pointers are checked at launch).
+static bool ttm_narrow_view(const ModeView& v, int64_t K) {
+    return v.J <= 32 && K >= 1 && K <= 16 && v.L % 8 == 0 && v.L >= 64;
+}
+
+template <typename T, int JN>
+static int launch_ttm_narrow(const T* y, const ModeView& v, const double* m, int64_t K,
+                             int64_t ldm, int transpose, T* z, hipStream_t st) {
+    constexpr int U = sizeof(T) == 8 ? kNarrowTtmStepsF64 : kNarrowTtmStepsF32;
+    constexpr int SC = 16 * (16 / (int)sizeof(T));
+    const int64_t nsteps = v.B * ((v.L + SC - 1) / SC);
+    const int64_t per_wg = (int64_t)kNarrowTtmWaves * U;
+    const int64_t cap = 2 * (int64_t)device_cu_count();
+    int64_t P = (nsteps + per_wg - 1) / per_wg;
+    P = P < 1 ? 1 : P > cap ? cap : P;
+    hipLaunchKernelGGL((ttm_narrow_f64<T, JN, U>), dim3((int)P), dim3(kNarrowTtmThreads), 0, st,
+                       y, v.L, v.J, m, ldm, (int)K, transpose, nsteps, (int)P, z);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+template <typename T>
+static int dispatch_ttm_narrow(const T* y, const ModeView& v, const double* m, int64_t K,
+                               int64_t ldm, int transpose, T* z, hipStream_t st) {
+    return v.J <= 16 ? launch_ttm_narrow<T, 16>(y, v, m, K, ldm, transpose, z, st)
+                     : launch_ttm_narrow<T, 32>(y, v, m, K, ldm, transpose, z, st);
+}
+
 // ------------------------------------------------------------------ host
 
 static int round_pow2(int v, int lo) {
@@ -191,6 +316,14 @@ int launch_ttm_mixed(const float* y, const ModeView& v, const double* m, int64_t
 
 int launch_ttm(const void* y, int dtype, const ModeView& v, const double* m, int64_t K,
                int64_t ldm, int transpose, int precision, void* z, hipStream_t st) {
+    // Narrow modes: FP64 arithmetic at streaming speed, which meets the error
+    // bound of every precision option (16-byte vector loads and stores need
+    // both data pointers aligned to 16 bytes).
+    if (ttm_narrow_view(v, K) && (uintptr_t)y % 16 == 0 && (uintptr_t)z % 16 == 0) {
+        if (dtype == TK_F64)
+            return dispatch_ttm_narrow((const double*)y, v, m, K, ldm, transpose, (double*)z, st);
+        return dispatch_ttm_narrow((const float*)y, v, m, K, ldm, transpose, (float*)z, st);
+    }
     if (precision == TK_TTM_FP64) {
         if (dtype == TK_F64)
             return dispatch_ttm((const double*)y, v, m, K, ldm, transpose, (double*)z, st);

@@ -139,6 +139,55 @@ def test_ttm_matches_oracle(dims, n, k, transpose, dtype):
     assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
 
 
+# Narrow modes (J <= 32, K <= 16, rows of Y_(n) made of runs of L contiguous
+# elements, L a multiple of 8): the TTM runs in FP64 arithmetic without LDS
+# whatever precision is asked for, so the FP64 bound (plus one rounding to
+# FP32) holds for every option.  Ragged last steps, several slabs, J = 5 and
+# J > 16, K = 1 and K = 16, a large case with many steps per wave; offset = 1
+# misaligns the input pointer, which sends the call to the tiled kernels.
+NARROW_TTM_CASES = [
+    ((96, 16, 7), 1, 8),
+    ((200, 5, 3), 1, 3),
+    ((72, 20, 2), 1, 16),
+    ((64, 32, 3), 1, 1),
+    ((8, 8, 5, 9), 2, 4),
+    ((1 << 20, 16), 1, 8),
+    ((1 << 18, 3, 11), 1, 2),
+]
+NARROW_TTM_OPTIONS = [  # (dtype, precision, offset)
+    (torch.float64, "fp64", 0), (torch.float64, "fp64", 1),
+    (torch.float32, "fp64", 0), (torch.float32, "fp64", 1),
+    (torch.float32, "bf16x3", 0), (torch.float32, "bf16", 0),
+]
+
+
+@pytest.mark.parametrize("dtype,precision,offset", NARROW_TTM_OPTIONS)
+@pytest.mark.parametrize("transpose", [True, False])
+@pytest.mark.parametrize("dims,n,k", NARROW_TTM_CASES)
+def test_ttm_narrow_modes(dims, n, k, transpose, dtype, precision, offset):
+    say(f"narrow ttm dims={dims} mode={n} K={k} transpose={transpose} {dtype} {precision} "
+        f"offset={offset}")
+    x = synth.random_tensor(dims, seed=5 * sum(dims) + k, dtype=dtype)
+    xh = x.double().numpy()
+    buf = torch.empty(xh.size + offset, dtype=dtype, device="cuda:0")
+    xd = buf[offset:].view(tuple(reversed(dims))).permute(*reversed(range(len(dims))))
+    xd.copy_(to_dev(x))
+    rng = np.random.default_rng(k + dims[n])
+    v = rng.standard_normal((k, dims[n]))           # op(M), K x J_n
+    m = v.T if transpose else v
+    md = tucker.empty_colmajor(m.shape[0], m.shape[1], "cuda:0").copy_(
+        torch.as_tensor(np.asfortranarray(m)))
+    z = tucker.ttm(xd, n, md, transpose=transpose, precision=precision)
+    torch.cuda.synchronize()
+    ref = oracle.ttm(xh, n, v)
+    tol = ttm_tolerance(xh, n, v)
+    if dtype == torch.float32:  # output rounded to FP32 once
+        tol = tol + U32 * np.abs(ref)
+    err = np.abs(to_host(z).astype(np.float64) - ref)
+    assert err.shape == ref.shape
+    assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
+
+
 def _compare_tucker(xh, res, ref, eps_sym):
     """Compare a GPU ST-HOSVD with the oracle's: ranks exactly; spectra and
     reconstructions within FP64 perturbation bounds."""
