@@ -102,7 +102,11 @@ typedef enum tk_gram_precision {
     TK_SVD_QR = 2
 } tk_gram_precision;
 
-/* Arithmetic of the tensor-times-matrix product. */
+/* Arithmetic of the tensor-times-matrix product: the least accurate
+ * arithmetic a call may use.  Narrow modes (J_n <= 32, K <= 16,
+ * L = prod_{k<n} I_k a multiple of 8 and at least 64, both data pointers
+ * 16-byte aligned) always run in FP64 arithmetic, which streams as fast
+ * there and meets every option's error bound. */
 typedef enum tk_ttm_precision {
     TK_TTM_FP64 = 0,   /* FP64 products and accumulation (FP64 or FP32 storage) */
     TK_TTM_BF16 = 1,   /* FP32 storage: operands rounded to bf16, FP32 accumulation */

@@ -13,7 +13,8 @@
 // bitwise reproducible) and mirrors the upper blocks into both triangles.
 //
 // FP64 path: v_mfma_f64_16x16x4f64 on FP64 data (FP32 input is widened
-// exactly while staging).
+// exactly while staging).  Narrow modes (J <= 32 over long contiguous runs)
+// replace stage 1 by gram_narrow_f64, which needs no LDS tile.
 #include "tile_io.hpp"
 #include "tk_common.hpp"
 

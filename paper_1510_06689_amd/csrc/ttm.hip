@@ -12,7 +12,9 @@
 // less matrix throughput than HBM delivers, so idle MFMA slots cost nothing.
 // The MFMA operand order is chosen so that the lanes of a quarter-wave
 // write consecutive output addresses: when the output's rows are contiguous
-// (L >= 16) the kernel forms Z blocks, otherwise Z^T blocks.
+// (L >= 16) the kernel forms Z blocks, otherwise Z^T blocks.  Narrow modes
+// (J <= 32, K <= 16 over long contiguous runs) take ttm_narrow_f64 instead,
+// whatever precision is asked for.
 #include "tile_io.hpp"
 #include "tk_common.hpp"
 
