@@ -103,7 +103,7 @@ typedef enum tk_gram_precision {
 } tk_gram_precision;
 
 /* Arithmetic of the tensor-times-matrix product: the least accurate
- * arithmetic a call may use.  Narrow modes (J_n <= 32, K <= 16,
+ * arithmetic a call may use.  Narrow modes (J_n <= 64, K <= 16,
  * L = prod_{k<n} I_k a multiple of 8 and at least 64, both data pointers
  * 16-byte aligned) always run in FP64 arithmetic, which streams as fast
  * there and meets every option's error bound. */

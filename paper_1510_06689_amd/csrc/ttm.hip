@@ -13,7 +13,7 @@
 // The MFMA operand order is chosen so that the lanes of a quarter-wave
 // write consecutive output addresses: when the output's rows are contiguous
 // (L >= 16) the kernel forms Z blocks, otherwise Z^T blocks.  Narrow modes
-// (J <= 32, K <= 16 over long contiguous runs) take ttm_narrow_f64 instead,
+// (J <= 64, K <= 16 over long contiguous runs) take ttm_narrow_f64 instead,
 // whatever precision is asked for.
 #include "tile_io.hpp"
 #include "tk_common.hpp"
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kTtmThreads) void ttm_f64_kernel(
 
 // ------------------------------------------------------------ narrow modes
 //
-// J <= 32 and K <= 16 where the rows of Y_(n) and Z_(n) are made of runs of
+// J <= 64 and K <= 16 where the rows of Y_(n) and Z_(n) are made of runs of
 // L contiguous elements (L a multiple of 8): no LDS.  A step is 16 E
 // consecutive l of one slab b (E = 16 bytes / element size).  In k-step s
 // lane t holds A[t % 16][4 s + t / 16] (op(M), FP64, loaded once) and reads
@@ -206,17 +206,19 @@ __global__ __launch_bounds__(kNarrowTtmThreads) void ttm_narrow_f64(
     }
 }
 
-constexpr int kNarrowTtmStepsF32 = 2, kNarrowTtmStepsF64 = 2;  // U: steps per batch
+// U: steps per batch (one at J <= 64, where a step already holds 16 loads)
+template <int JN>
+constexpr int kNarrowTtmSteps = JN == 64 ? 1 : 2;
 
 // Views the narrow TTM takes (the data pointers are checked at launch).
 static bool ttm_narrow_view(const ModeView& v, int64_t K) {
-    return v.J <= 32 && K >= 1 && K <= 16 && v.L % 8 == 0 && v.L >= 64;
+    return v.J <= 64 && K >= 1 && K <= 16 && v.L % 8 == 0 && v.L >= 64;
 }
 
 template <typename T, int JN>
 static int launch_ttm_narrow(const T* y, const ModeView& v, const double* m, int64_t K,
                              int64_t ldm, int transpose, T* z, hipStream_t st) {
-    constexpr int U = sizeof(T) == 8 ? kNarrowTtmStepsF64 : kNarrowTtmStepsF32;
+    constexpr int U = kNarrowTtmSteps<JN>;
     constexpr int SC = 16 * (16 / (int)sizeof(T));
     const int64_t nsteps = v.B * ((v.L + SC - 1) / SC);
     const int64_t per_wg = (int64_t)kNarrowTtmWaves * U;
@@ -232,8 +234,9 @@ static int launch_ttm_narrow(const T* y, const ModeView& v, const double* m, int
 template <typename T>
 static int dispatch_ttm_narrow(const T* y, const ModeView& v, const double* m, int64_t K,
                                int64_t ldm, int transpose, T* z, hipStream_t st) {
-    return v.J <= 16 ? launch_ttm_narrow<T, 16>(y, v, m, K, ldm, transpose, z, st)
-                     : launch_ttm_narrow<T, 32>(y, v, m, K, ldm, transpose, z, st);
+    if (v.J <= 16) return launch_ttm_narrow<T, 16>(y, v, m, K, ldm, transpose, z, st);
+    if (v.J <= 32) return launch_ttm_narrow<T, 32>(y, v, m, K, ldm, transpose, z, st);
+    return launch_ttm_narrow<T, 64>(y, v, m, K, ldm, transpose, z, st);
 }
 
 // ------------------------------------------------------------------ host

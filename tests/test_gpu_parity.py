@@ -139,14 +139,19 @@ def test_ttm_matches_oracle(dims, n, k, transpose, dtype):
     assert np.all(err <= tol), f"max err/tol {np.max(err / tol)}"
 
 
-# Narrow modes (J <= 32, K <= 16, rows of Y_(n) made of runs of L contiguous
+# Narrow modes (J <= 64, K <= 16, rows of Y_(n) made of runs of L contiguous
 # elements, L a multiple of 8): the TTM runs in FP64 arithmetic without LDS
 # whatever precision is asked for, so the FP64 bound (plus one rounding to
-# FP32) holds for every option.  Ragged last steps, several slabs, J = 5 and
-# J > 16, K = 1 and K = 16, a large case with many steps per wave; offset = 1
-# misaligns the input pointer, which sends the call to the tiled kernels.
+# FP32) holds for every option.  Ragged last steps, several slabs, J = 5,
+# 16 < J <= 32 and 32 < J <= 64, K = 1 and K = 16, a large case with many
+# steps per wave; offset = 1 misaligns the input pointer, which sends the
+# call to the tiled kernels.
 NARROW_TTM_CASES = [
     ((96, 16, 7), 1, 8),
+    ((64, 64, 3), 1, 16),
+    ((200, 40, 2), 1, 5),
+    ((72, 33, 3), 1, 16),
+    ((1 << 16, 64, 4), 1, 16),
     ((200, 5, 3), 1, 3),
     ((72, 20, 2), 1, 16),
     ((64, 32, 3), 1, 1),
