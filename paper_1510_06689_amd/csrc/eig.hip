@@ -3,12 +3,16 @@
 // this is the same family of method on one workgroup):
 //
 //   1. Householder reduction to tridiagonal form T = Q^T S Q.  Each step
-//      forms A22 x (x = the pivot row, read from the upper part) and |x|^2
-//      in one pass, derives the reflector, then applies the symmetric
-//      rank-2 update with a commutative formula so A stays exactly
-//      symmetric (three barriers per step).  The matrix lives in LDS for
-//      J <= 128, otherwise in global scratch; reflector k is kept in
-//      column k below the diagonal and copied to global scratch at the end;
+//      forms A22 x (x = the pivot row) and |x|^2 in one pass, derives the
+//      reflector, then applies the symmetric rank-2 update with a
+//      commutative formula so A stays exactly symmetric.  For J <= 128 the
+//      matrix lives in registers; otherwise it lives in global scratch and
+//      the first J - 128 columns are reduced in panels of eight (the rank-2
+//      updates of a panel are kept as vectors in LDS, applied to the pivot
+//      rows and to A22 x on the fly and to the trailing block once per
+//      panel, as in LAPACK's latrd) before the last 128 x 128 block moves to
+//      registers; reflector k is kept in column k below the diagonal and
+//      copied to global scratch at the end;
 //   2. all eigenvalues of T by multisection: groups of threads per
 //      eigenvalue evaluate Sturm counts with the three-term determinant
 //      recurrence of T scaled by a power of two (exact), rescaled by 2^+-300
@@ -33,6 +37,7 @@ namespace tk {
 constexpr int kEigThreads = 1024;
 constexpr int kEigWaves = kEigThreads / 64;
 constexpr int kInvIters = 2;
+constexpr int kPanel = 8;  // columns per panel of the global-memory reduction
 constexpr int kLuArrays = 6;  // u0 (reciprocal), u1, u2, multiplier, pivot flag, x
 constexpr int kMaxVecSlots = TK_MAX_MODE_DIM / 64;  // per-lane elements of one vector
 
@@ -360,51 +365,92 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     // its 126 reflectors at pitch 128).
     const bool hybrid = J > 128 && region >= 126 * 128;
     const int kend = hybrid ? J - 128 : J - 2;
-    for (int k = 0; k < kend; ++k) {
-        const int m = J - k - 1;
-        const double* x = A + (size_t)k * J + (k + 1);  // row k, columns k+1.. (= column k)
-        // w = A22 x (A22 is symmetric: read column i so a wave's loads are contiguous)
-        {
-            double acc = 0.0;
-            if (mi < m) {
-#pragma unroll 8
-                for (int j = mc; j < m; j += C) acc += A[(size_t)(k + 1 + j) * J + (k + 1 + mi)] * x[j];
+    // Panels of kPanel columns (LAPACK's latrd scheme): inside a panel A keeps
+    // its values from the panel start, and column q of the panel leaves
+    // v_q and w_q = p_q - (kc_q) v_q in LDS (Vs, Ws), so that the matrix the
+    // reduction has reached is A - sum_q (v_q w_q^T + w_q v_q^T).  Row k and
+    // row k + 1 are corrected by those terms, A22 x is formed from the panel
+    // start's A22 and corrected by V (W^T x) + W (V^T x); after the panel the
+    // trailing block takes all of its rank-2 updates in one pass, in a
+    // commutative form so that A stays exactly symmetric.  A22 is read once
+    // per column and written once per panel.
+    double* Vs = reg;              // [kPanel][J], indexed by row of A
+    double* Ws = reg + kPanel * J;
+    double* xs = lam;              // corrected row k (columns k + 1 ..)
+    double* a0s = shift;           // corrected row k + 1 (columns k + 1 ..)
+    for (int k0 = 0; k0 < kend; k0 += kPanel) {
+        const int nq = min(kPanel, kend - k0);
+        for (int c = 0; c < nq; ++c) {
+            const int k = k0 + c, m = J - k - 1;
+            for (int j = tid; j < m; j += kEigThreads) {
+                const int g = k + 1 + j;
+                double xv = A[(size_t)k * J + g], av = A[(size_t)(k + 1) * J + g];
+                for (int q = 0; q < c; ++q) {
+                    const double vg = Vs[q * J + g], wg = Ws[q * J + g];
+                    xv -= Vs[q * J + k] * wg + Ws[q * J + k] * vg;
+                    av -= Vs[q * J + k + 1] * wg + Ws[q * J + k + 1] * vg;
+                }
+                xs[j] = xv;
+                a0s[j] = av;
             }
-            part[mc * rb + mi] = acc;
-        }
-        double sq = 0.0;
-        for (int j = 1 + lane; j < m; j += 64) sq += x[j] * x[j];
-        const double sigma = wave_sum(sq);  // same bits in every wave
-        const double x0 = x[0];
-        double b, mu, v0;
-        if (sigma == 0.0) {
-            b = 0.0;
-            mu = x0;
-            v0 = 1.0;
-        } else {
-            mu = sqrt(x0 * x0 + sigma);
-            v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
-            b = 2.0 * v0 * v0 / (sigma + v0 * v0);
-        }
-        const double inv_v0 = 1.0 / v0;
-        if (tid == 0) {
-            d[k] = A[(size_t)k * J + k];
-            e[k] = mu;
-            beta[k] = b;
-        }
-        __syncthreads();
-        if (b != 0.0) {
-            // v = (x - mu e_1) / v0, so p = b A22 v = b (A22 x - mu A22 e_1) / v0;
-            // A22 e_1 is row 0 of A22.  Every wave forms kc = b/2 p.v from the
-            // partials itself (same order, same bits).
-            const double* a0 = A + (size_t)(k + 1) * J + (k + 1);
+            __syncthreads();
+            // A22 x with the panel start's A22 (read column i so that a
+            // wave's loads are contiguous)
+            {
+                double acc = 0.0;
+                if (mi < m) {
+#pragma unroll 8
+                    for (int j = mc; j < m; j += C)
+                        acc += A[(size_t)(k + 1 + j) * J + (k + 1 + mi)] * xs[j];
+                }
+                part[mc * rb + mi] = acc;
+            }
+            // red[q] = v_q . x, red[c + q] = w_q . x (one wave each)
+            if (wave < 2 * c) {
+                const double* vec = wave < c ? Vs + wave * J : Ws + (wave - c) * J;
+                double sdot = 0.0;
+                for (int j = lane; j < m; j += 64) sdot += vec[k + 1 + j] * xs[j];
+                sdot = wave_sum(sdot);
+                if (lane == 0) red[wave] = sdot;
+            }
+            double sq = 0.0;
+            for (int j = 1 + lane; j < m; j += 64) sq += xs[j] * xs[j];
+            const double sigma = wave_sum(sq);  // same bits in every wave
+            const double x0 = xs[0];
+            double b, mu, v0;
+            if (sigma == 0.0) {
+                b = 0.0;
+                mu = x0;
+                v0 = 1.0;
+            } else {
+                mu = sqrt(x0 * x0 + sigma);
+                v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
+                b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+            }
+            const double inv_v0 = 1.0 / v0;
+            if (tid == 0) {
+                double dk = A[(size_t)k * J + k];
+                for (int q = 0; q < c; ++q) {
+                    const double vk = Vs[q * J + k], wk = Ws[q * J + k];
+                    dk -= vk * wk + wk * vk;
+                }
+                d[k] = dk;
+                e[k] = mu;
+                beta[k] = b;
+            }
+            __syncthreads();
+            // v = (x - mu e_1) / v0, so p = b A22 v = b (A22 x - mu A22 e_1) / v0
+            // with A22 e_1 = row k + 1.  Every wave forms kc2 = b p.v from the
+            // partials itself (same order, same bits); wave 0 keeps p, v.
             double pv = 0.0;
             for (int j = lane; j < m; j += 64) {
                 double wj = 0.0;
 #pragma unroll 8
-                for (int c = 0; c < C; ++c) wj += part[c * rb + j];
-                const double pj = b * (wj - mu * a0[j]) * inv_v0;
-                const double vj = j == 0 ? 1.0 : x[j] * inv_v0;
+                for (int cc = 0; cc < C; ++cc) wj += part[cc * rb + j];
+                for (int q = 0; q < c; ++q)
+                    wj -= Vs[q * J + k + 1 + j] * red[c + q] + Ws[q * J + k + 1 + j] * red[q];
+                const double pj = b * (wj - mu * a0s[j]) * inv_v0;
+                const double vj = j == 0 ? 1.0 : xs[j] * inv_v0;
                 pv += pj * vj;
                 if (wave == 0) {
                     pp[j] = pj;
@@ -412,21 +458,43 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
                 }
             }
             const double kc2 = b * wave_sum(pv);  // 2 kc
-            __syncthreads();
-            // A22 -= v p^T + p v^T - 2 kc v v^T, in a commutative form so that
-            // A stays exactly symmetric
-#pragma unroll 4
-            for (int i = wave; i < m; i += kEigWaves) {
-                const double vi = vv[i], pi = pp[i];
-                double* row = A + (size_t)(k + 1 + i) * J + (k + 1);
+            if (wave == 0) {
+                // v p^T + p v^T - 2 kc v v^T = v w^T + w v^T with w = p - kc v;
+                // b = 0 leaves v = w = 0 (no reflection).  Lane j reads the
+                // pp, vv entries it wrote itself.
                 for (int j = lane; j < m; j += 64) {
-                    const double vj = vv[j], pj = pp[j];
-                    const double t = __dadd_rn(__dmul_rn(vi, pj), __dmul_rn(pi, vj));
-                    row[j] -= __dsub_rn(t, __dmul_rn(kc2, __dmul_rn(vi, vj)));
+                    const double vj = b != 0.0 ? vv[j] : 0.0;
+                    const double wj = b != 0.0 ? pp[j] - 0.5 * kc2 * vv[j] : 0.0;
+                    Vs[c * J + k + 1 + j] = vj;
+                    Ws[c * J + k + 1 + j] = wj;
+                    // the reflector goes below the diagonal of column k
+                    if (b != 0.0) A[(size_t)(k + 1 + j) * J + k] = vj;
                 }
             }
-            // the reflector goes below the diagonal of column k (no longer read)
-            for (int j = tid; j < m; j += kEigThreads) A[(size_t)(k + 1 + j) * J + k] = vv[j];
+            __syncthreads();
+        }
+        // trailing block (rows and columns from k0 + nq) takes the panel's
+        // updates: thread t owns columns t % 256 (+ 256) and rows t / 256 + 4 i
+        const int t0 = k0 + nq, mt = J - t0;
+        const int jc = tid & 255, ir = tid >> 8;
+        for (int jb = jc; jb < mt; jb += 256) {
+            double vj[kPanel], wj[kPanel];
+#pragma unroll
+            for (int q = 0; q < kPanel; ++q) {
+                vj[q] = q < nq ? Vs[q * J + t0 + jb] : 0.0;
+                wj[q] = q < nq ? Ws[q * J + t0 + jb] : 0.0;
+            }
+            for (int i = ir; i < mt; i += 4) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < kPanel; ++q) {
+                    if (q < nq) {
+                        const double vi = Vs[q * J + t0 + i], wi = Ws[q * J + t0 + i];
+                        t = __dadd_rn(t, __dadd_rn(__dmul_rn(vi, wj[q]), __dmul_rn(wi, vj[q])));
+                    }
+                }
+                A[(size_t)(t0 + i) * J + t0 + jb] -= t;
+            }
         }
         __syncthreads();
     }

@@ -252,6 +252,12 @@ STHOSVD_CASES = [
     ((50,), (5,), 1.0, 1e-2, None, None),                         # N = 1
     ((130, 70), (10, 10), 0.5, 1e-5, None, None),                 # N = 2, ragged blocks
     ((8, 8, 8, 8, 8), (2, 3, 2, 3, 2), 0.9, 1e-3, (4, 3, 2, 1, 0), None),
+    # extents above 128: the tridiagonal reduction runs in global memory for
+    # J - 128 columns (in panels of eight, the last one partial) before the
+    # register finish; at J = 512 the whole reduction stays in global memory
+    ((200, 40, 6), (10, 6, 3), 0.8, 1e-4, None, None),
+    ((300, 20, 4), (12, 5, 3), 0.7, 1e-4, None, None),            # rank-deficient Gram
+    ((512, 12, 3), (8, 4, 2), 0.7, 1e-3, None, None),
 ]
 
 
