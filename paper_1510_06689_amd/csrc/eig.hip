@@ -318,7 +318,12 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
 
 // JP = 32, 64, 128: A lives in registers during the tridiagonalisation
 // (J <= JP); JP = 0: A lives in the global scratch (J > 128).
-template <int JP>
+// PH = 0: the whole solver in one launch.  PH = 1: steps 1 and the scaling of
+// T, then T, beta and the bounds go to the hand-off area (the first 6 J + 4
+// doubles of the scratch, A's area, unused or free by then) and the launch
+// ends; eig_multisect then finds the eigenvalues with one workgroup each and
+// PH = 3 picks everything up for steps 3 to 5.
+template <int JP, int PH>
 __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     extern __shared__ double smem[];
     const int J = a.J;
@@ -338,7 +343,10 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     int* misc = (int*)(red + 64);  // [0] = R
     double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
     double* X = a.u;                          // column-major J x R
+    double* ho = a.scratch;                   // hand-off between split launches
+    double sc, tnorm;
 
+    if constexpr (PH != 3) {
     if constexpr (JP > 0) {
     // ---- 1. Householder tridiagonalisation, A in registers ---------------
     tridiag_regs<JP>(a.s, J, J, 0, J, reg, red, d, e, beta, H);
@@ -536,13 +544,25 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         red[35] = tnorm;
     }
     __syncthreads();
-    const double sc = red[34], tnorm = red[35];
+    sc = red[34];
+    tnorm = red[35];
     double* ds = dots;  // scaled diagonal
     for (int i = tid; i < J; i += kEigThreads) {
         ds[i] = d[i] * sc;
         e2[i] = (e[i] * sc) * (e[i] * sc);
     }
     __syncthreads();
+    if constexpr (PH == 1) {
+        for (int i = tid; i < J; i += kEigThreads) {
+            ho[i] = d[i];
+            ho[J + i] = e[i];
+            ho[2 * J + i] = beta[i];
+            ho[3 * J + i] = ds[i];
+            ho[4 * J + i] = e2[i];
+        }
+        if (tid < 4) ho[5 * J + tid] = red[32 + tid];  // gl, gu, sc, tnorm
+        return;
+    }
 
     // ---- 2. eigenvalues by multisection ---------------------------------
     {
@@ -575,6 +595,18 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         }
     }
     __syncthreads();
+    } else {
+        for (int i = tid; i < J; i += kEigThreads) {
+            d[i] = ho[i];
+            e[i] = ho[J + i];
+            beta[i] = ho[2 * J + i];
+            lam[i] = ho[5 * J + 4 + i];
+        }
+        sc = ho[5 * J + 2];
+        tnorm = ho[5 * J + 3];
+        __syncthreads();
+    }
+    (void)sc;
     // Jordan-Wielandt input: the leading half of the spectrum is sigma(R)
     const int Jv = a.aug ? J / 2 : J;
     auto val = [&](int r) {
@@ -847,9 +879,42 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     }
 }
 
-template <int JP>
+template <int JP, int PH>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region) {
-    eig_body<JP>(a, region);
+    eig_body<JP, PH>(a, region);
+}
+
+// Step 2 of a split solve: workgroup k (one wave) finds eigenvalue k (k-th
+// smallest) of the scaled T in the hand-off area by multisection with 64
+// sample points per round (65 sub-intervals, six bits per round), the same
+// Sturm counts and stopping rule as the one-launch solver, and stores it,
+// unscaled, at position J - 1 - k of the descending list.
+__global__ __launch_bounds__(64) void eig_multisect(double* __restrict__ ho, int J) {
+    extern __shared__ double sm[];
+    double* ds = sm;
+    double* e2 = sm + J;
+    const int k = blockIdx.x, lane = threadIdx.x;
+    for (int i = lane; i < J; i += 64) {
+        ds[i] = ho[3 * J + i];
+        e2[i] = ho[4 * J + i];
+    }
+    __syncthreads();
+    double lo = ho[5 * J], hi = ho[5 * J + 1];
+    const double sc = ho[5 * J + 2];
+    const double atol = 2.0 * DBL_EPSILON;  // T is scaled to norm <= 1
+    for (int it = 0; it < 160; ++it) {
+        const double tol = fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
+        if (hi - lo <= tol) break;  // lo, hi are the same in every lane
+        const double h = (hi - lo) / 65.0;
+        const int c = sturm_count(ds, e2, J, lo + h * (double)(lane + 1));
+        const uint64_t bal = __ballot(c > k);
+        const int sstar = bal ? __ffsll((long long)bal) : 65;  // 1-based point
+        const double nlo = sstar == 1 ? lo : lo + h * (double)(sstar - 1);
+        const double nhi = sstar == 65 ? hi : lo + h * (double)sstar;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) ho[5 * J + 4 + (J - 1 - k)] = 0.5 * (lo + hi) / sc;
 }
 
 // One workgroup per problem of a batch.  conditional != 0: only problems whose
@@ -865,7 +930,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __rest
         if (!(a.flags[0] & 4)) return;  // uniform over the workgroup
         a.guard = 0.0;
     }
-    eig_body<JP>(a, region);
+    eig_body<JP, 0>(a, region);
     if (conditional) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -903,23 +968,40 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
     return TK_OK;
 }
 
+// Extents of at least kSplitEig take three launches (reduction, multisection
+// over J workgroups, vectors): the multisection then runs on the whole GPU.
+constexpr int kSplitEig = 64;
+
+template <int JP, int PH>
+static int launch_eig_phase(const EigArgs& a, int region, size_t lds, hipStream_t st) {
+    auto fn = eig_kernel<JP, PH>;
+    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+template <int JP>
+static int launch_eig_jp(const EigArgs& a, int region, size_t lds, hipStream_t st) {
+    if (a.J < kSplitEig) return launch_eig_phase<JP, 0>(a, region, lds, st);
+    TK_TRY((launch_eig_phase<JP, 1>(a, region, lds, st)));
+    hipLaunchKernelGGL(eig_multisect, dim3(a.J), dim3(64), (size_t)2 * a.J * sizeof(double), st,
+                       a.scratch, a.J);
+    TK_HIP(hipGetLastError());
+    return launch_eig_phase<JP, 3>(a, region, lds, st);
+}
+
 int launch_eig(const EigArgs& a, hipStream_t st) {
     const int JP = a.J <= 32 ? 32 : a.J <= 64 ? 64 : a.J <= 128 ? 128 : 0;
     const int region = (int)eig_region_doubles_jp(a.J, JP);
     const size_t lds = ((size_t)region + eig_small_doubles(a.J)) * sizeof(double);
-    if (a.J <= 128) {
-        auto fn = a.J <= 32 ? eig_kernel<32> : a.J <= 64 ? eig_kernel<64> : eig_kernel<128>;
-        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
-    } else {
-        auto fn = eig_kernel<0>;
-        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL(fn, dim3(1), dim3(kEigThreads), lds, st, a, region);
+    switch (JP) {
+        case 32: return launch_eig_jp<32>(a, region, lds, st);
+        case 64: return launch_eig_jp<64>(a, region, lds, st);
+        case 128: return launch_eig_jp<128>(a, region, lds, st);
+        default: return launch_eig_jp<0>(a, region, lds, st);
     }
-    TK_HIP(hipGetLastError());
-    return TK_OK;
 }
 
 }  // namespace tk
