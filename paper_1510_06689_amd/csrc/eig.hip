@@ -27,7 +27,9 @@
 //      vector in registers (no barriers), and a sign rule (largest |entry|
 //      positive, lowest index on ties), written to the factor output.
 // Barriers never wait on global stores inside loops: global memory is only
-// written between phases.  One workgroup of 1024 threads; no host sync.
+// written between phases.  One workgroup of 1024 threads, except that from
+// J = 64 on step 2 runs in a launch of its own (eig_multisect, one wave per
+// eigenvalue) between two launches of the solver; no host sync.
 #include <cfloat>
 
 #include "tk_common.hpp"
