@@ -155,6 +155,23 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_f64(
                                       partial + (int64_t)p * npairs * 256, lds);
 }
 
+// acc + partial[q n + idx] over q = g, g + 4, ... < P, added in that order;
+// eight loads go out per trip so that they overlap.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int P,
+                                               int n, int idx, int g) {
+    double acc = 0.0;
+    int q = g;
+    for (; q + 28 < P; q += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(q + 4 * u) * n + idx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q < P; q += 4) acc += partial[(int64_t)q * n + idx];
+    return acc;
+}
+
 // S[r + J c] for the upper block pairs.  Each workgroup reduces 64 outputs;
 // its 4 wave-sized groups sum the partials p = g, g + 4, ... and the four
 // group sums are added in a fixed order.
@@ -165,9 +182,7 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ pa
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int idx = blockIdx.x * 64 + o;
     const int n = npairs * 256;
-    double acc = 0.0;
-    if (idx < n)
-        for (int q = g; q < P; q += 4) acc += partial[(int64_t)q * n + idx];
+    const double acc = idx < n ? sum_partials(partial, P, n, idx, g) : 0.0;
     part[g][o] = acc;
     __syncthreads();
     if (g != 0 || idx >= n) return;
@@ -466,9 +481,7 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
     const int P = *tk.nparts;  // slots the Gram launch wrote (<= tk.P)
     if (w < tk.nwg - 1 || tk.nu == nullptr) {
         const int idx = w * 64 + o;
-        double acc = 0.0;
-        if (idx < n)
-            for (int q = g; q < P; q += 4) acc += tk.partial[(int64_t)q * n + idx];
+        const double acc = idx < n ? sum_partials(tk.partial, P, n, idx, g) : 0.0;
         part[g][o] = acc;
         __syncthreads();
         if (g != 0 || idx >= n) return;
