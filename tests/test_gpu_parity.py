@@ -106,6 +106,32 @@ def test_gram_is_deterministic():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_narrow_gram_and_ttm_are_deterministic(dtype):
+    # the narrow kernels fold fixed per-wave partials in a fixed order
+    x = to_dev(synth.random_tensor((1 << 14, 24, 9), seed=6, dtype=dtype))
+    a, sa = tucker.gram(x, 1)
+    b, sb = tucker.gram(x, 1)
+    u = tucker.empty_colmajor(24, 8, "cuda:0").copy_(
+        torch.as_tensor(np.asfortranarray(np.random.default_rng(6).standard_normal((24, 8)))))
+    za = tucker.ttm(x, 1, u, transpose=True)
+    zb = tucker.ttm(x, 1, u, transpose=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(sa, sb) and torch.equal(za, zb)
+
+
+def test_sthosvd_is_deterministic():
+    # extents 64 .. 200 run the eigensolver in three launches (the
+    # multisection over one workgroup per eigenvalue) and the panel reduction
+    x = to_dev(synth.planted_tucker((200, 96, 64), (10, 8, 6), rho=0.8, noise=1e-4, seed=8))
+    r1 = tucker.sthosvd(x, 1e-3)
+    r2 = tucker.sthosvd(x, 1e-3)
+    assert r1.ranks == r2.ranks
+    assert torch.equal(r1.core, r2.core)
+    for u1, u2, l1, l2 in zip(r1.factors, r2.factors, r1.eigvals, r2.eigvals):
+        assert torch.equal(u1, u2) and torch.equal(l1, l2)
+
+
 TTM_CASES = [
     ((32, 32, 32), 0, 4), ((32, 32, 32), 1, 5), ((32, 32, 32), 2, 6),
     ((5, 7, 3), 1, 2), ((128, 64, 16), 0, 16), ((128, 64, 16), 1, 17),
