@@ -318,6 +318,13 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
     __syncthreads();
 }
 
+// Hand-off area of a split solve (6 J + 4 doubles): the start of the
+// scratch (A's area, J x J, unused or dead once step 1 is done) when it fits,
+// else the 64 spare doubles behind the reflectors (J <= 6).
+__host__ __device__ inline double* eig_handoff(double* scratch, int J) {
+    return 6 * J + 4 <= J * J ? scratch : scratch + (size_t)2 * J * J;
+}
+
 // JP = 32, 64, 128: A lives in registers during the tridiagonalisation
 // (J <= JP); JP = 0: A lives in the global scratch (J > 128).
 // PH = 0: the whole solver in one launch.  PH = 1: steps 1 and the scaling of
@@ -345,7 +352,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     int* misc = (int*)(red + 64);  // [0] = R
     double* H = a.scratch + (size_t)J * J;    // reflector k at H[k * J], length J - k - 1
     double* X = a.u;                          // column-major J x R
-    double* ho = a.scratch;                   // hand-off between split launches
+    double* ho = eig_handoff(a.scratch, J);   // hand-off between split launches
     double sc, tnorm;
 
     if constexpr (PH != 3) {
@@ -891,11 +898,10 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
 // sample points per round (65 sub-intervals, six bits per round), the same
 // Sturm counts and stopping rule as the one-launch solver, and stores it,
 // unscaled, at position J - 1 - k of the descending list.
-__global__ __launch_bounds__(64) void eig_multisect(double* __restrict__ ho, int J) {
-    extern __shared__ double sm[];
+__device__ __forceinline__ void multisect_one(double* __restrict__ ho, int J, int k, double* sm) {
     double* ds = sm;
     double* e2 = sm + J;
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x;
     for (int i = lane; i < J; i += 64) {
         ds[i] = ho[3 * J + i];
         e2[i] = ho[4 * J + i];
@@ -919,11 +925,29 @@ __global__ __launch_bounds__(64) void eig_multisect(double* __restrict__ ho, int
     if (lane == 0) ho[5 * J + 4 + (J - 1 - k)] = 0.5 * (lo + hi) / sc;
 }
 
+__global__ __launch_bounds__(64) void eig_multisect(double* __restrict__ scratch, int J) {
+    extern __shared__ double sm[];
+    multisect_one(eig_handoff(scratch, J), J, blockIdx.x, sm);
+}
+
+// The same for a batch: workgroup w takes eigenvalue w % jmax of problem
+// w / jmax (workgroups beyond that problem's J exit at once).
+__global__ __launch_bounds__(64) void eig_multisect_batched(const EigArgs* __restrict__ args,
+                                                            int jmax) {
+    extern __shared__ double sm[];
+    const int p = blockIdx.x / jmax, k = blockIdx.x - p * jmax;
+    const int J = args[p].J;
+    if (k >= J) return;  // uniform over the workgroup
+    multisect_one(eig_handoff(args[p].scratch, J), J, k, sm);
+}
+
 // One workgroup per problem of a batch.  conditional != 0: only problems whose
 // status word has the guard bit (4) run, on their FP64 Gram and without the
 // guard; afterwards the bit is cleared and `mode_bit` is recorded in the
-// problem's second status word.
-template <int JP>
+// problem's second status word.  PH as in eig_body: the unconditional pass
+// runs as PH = 1, eig_multisect_batched, PH = 3; the conditional one, which
+// few problems take, as one launch (PH = 0).
+template <int JP, int PH>
 __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __restrict__ args,
                                                            int region, int conditional,
                                                            int mode_bit) {
@@ -932,7 +956,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __rest
         if (!(a.flags[0] & 4)) return;  // uniform over the workgroup
         a.guard = 0.0;
     }
-    eig_body<JP, 0>(a, region);
+    eig_body<JP, PH>(a, region);
     if (conditional) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -961,13 +985,20 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
     // partition follows each problem's own J (region computed per J <= jmax)
     const int region = (int)eig_region_doubles_jp(jmax, 128);
     const size_t lds = ((size_t)region + eig_small_doubles(jmax)) * sizeof(double);
-    auto fn = eig_batched<128>;
-    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    hipLaunchKernelGGL(fn, dim3(count), dim3(kEigThreads), lds, st, args_dev, region, conditional,
-                       mode_bit);
+    auto launch = [&](auto fn) -> int {
+        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        hipLaunchKernelGGL(fn, dim3(count), dim3(kEigThreads), lds, st, args_dev, region,
+                           conditional, mode_bit);
+        TK_HIP(hipGetLastError());
+        return TK_OK;
+    };
+    if (conditional) return launch(eig_batched<128, 0>);
+    TK_TRY(launch(eig_batched<128, 1>));
+    hipLaunchKernelGGL(eig_multisect_batched, dim3(count * jmax), dim3(64),
+                       (size_t)2 * jmax * sizeof(double), st, args_dev, jmax);
     TK_HIP(hipGetLastError());
-    return TK_OK;
+    return launch(eig_batched<128, 3>);
 }
 
 // Extents of at least kSplitEig take three launches (reduction, multisection
