@@ -517,9 +517,11 @@ constexpr int kMtWaves = kMtThreads / 64;
 // NKB: 16-row blocks of op(M) per workgroup; NKS: 32-wide k-steps over J;
 // X3: split both operands (three products) instead of one bf16 product.
 // UNIT: columns contiguous (L == 1, J % 8 == 0), loaded as 16-byte vectors.
+// SKIP: row blocks at or beyond K skip their products (a batch sizes NKB for
+// the rank capacity, the rank comes later from the device).
 // The body stages rows [r0, r0 + 16 NKB) of op(M) and walks column blocks
 // wg, wg + nwg, ... (one block of 16 columns per wave at a time).
-template <int NKB, int NKS, bool X3, bool UNIT>
+template <int NKB, int NKS, bool X3, bool UNIT, bool SKIP = false>
 __device__ __forceinline__ void ttm_bf16_body(
     const float* __restrict__ y, int64_t L, int64_t ncols, int J, const double* __restrict__ m,
     int64_t ldm, int K, int transpose, float* __restrict__ z, int r0, int64_t wg, int64_t nwg,
@@ -548,6 +550,8 @@ __device__ __forceinline__ void ttm_bf16_body(
     __syncthreads();
 
     const int c16 = lane & 15, g4 = lane >> 4;
+    // row blocks that hold rows < K: the others' products are never stored
+    const int nkb = min(NKB, (K - r0 + 15) / 16);
     const int64_t nblk = (ncols + 15) / 16;
     const int64_t wstride = nwg * kMtWaves;
     const int64_t JL = (int64_t)J * L, KL = (int64_t)K * L;
@@ -594,6 +598,9 @@ __device__ __forceinline__ void ttm_bf16_body(
             }
 #pragma unroll
             for (int kb = 0; kb < NKB; ++kb) {
+                if constexpr (SKIP && NKB > 1) {
+                    if (kb >= nkb) break;  // uniform over the workgroup
+                }
                 const bf8_t ah = afr[(kb * NKS + ks) * 2][lane];
                 acc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh, acc[kb], 0, 0, 0);
                 if (X3) {
@@ -700,11 +707,11 @@ __global__ __launch_bounds__(kMtThreads) void ttm_bf16_batched(const BatchTtmTas
     const bool unit = mv.L == 1 && mv.J % 8 == 0 && ((uintptr_t)tk.y & 15) == 0 &&
                       ((uintptr_t)tk.z & 15) == 0;
     if (unit)
-        ttm_bf16_body<NKB, NKS, X3, true>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z, r0, w,
-                                          tk.v.nwg, afr);
+        ttm_bf16_body<NKB, NKS, X3, true, true>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z,
+                                                r0, w, tk.v.nwg, afr);
     else
-        ttm_bf16_body<NKB, NKS, X3, false>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z, r0, w,
-                                           tk.v.nwg, afr);
+        ttm_bf16_body<NKB, NKS, X3, false, true>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z,
+                                                 r0, w, tk.v.nwg, afr);
 }
 
 template <int NKB, int NKS, bool X3>
