@@ -893,12 +893,17 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(EigArgs a, int region)
     eig_body<JP, PH>(a, region);
 }
 
-// Step 2 of a split solve: workgroup k (one wave) finds eigenvalue k (k-th
-// smallest) of the scaled T in the hand-off area by multisection with 64
-// sample points per round (65 sub-intervals, six bits per round), the same
-// Sturm counts and stopping rule as the one-launch solver, and stores it,
-// unscaled, at position J - 1 - k of the descending list.
-__device__ __forceinline__ void multisect_one(double* __restrict__ ho, int J, int k, double* sm) {
+// Step 2 of a split solve by multisection on the scaled T in the hand-off
+// area: each group of TPE lanes of a wave finds one eigenvalue k (k-th
+// smallest) with TPE sample points per round (TPE + 1 sub-intervals), the
+// same Sturm counts and stopping rule as the one-launch solver, and stores
+// it, unscaled, at position J - 1 - k of the descending list.  TPE = 64 (one
+// eigenvalue per wave, six bits per round) suits a single solve, whose few
+// waves are latency-bound; a batch fills the GPU and is issue-bound, so
+// TPE = 16 (four eigenvalues per wave) does less work in all.
+template <int TPE>
+__device__ __forceinline__ void multisect_group(double* __restrict__ ho, int J, int k,
+                                                bool active, double* sm) {
     double* ds = sm;
     double* e2 = sm + J;
     const int lane = threadIdx.x;
@@ -907,38 +912,46 @@ __device__ __forceinline__ void multisect_one(double* __restrict__ ho, int J, in
         e2[i] = ho[4 * J + i];
     }
     __syncthreads();
+    if (!active) return;  // the whole group (k is the same in its lanes)
+    const int s = lane % TPE, gofs = lane - s;
+    const uint64_t gmask = TPE == 64 ? ~0ull : (((1ull << TPE) - 1ull) << gofs);
     double lo = ho[5 * J], hi = ho[5 * J + 1];
     const double sc = ho[5 * J + 2];
     const double atol = 2.0 * DBL_EPSILON;  // T is scaled to norm <= 1
     for (int it = 0; it < 160; ++it) {
         const double tol = fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
-        if (hi - lo <= tol) break;  // lo, hi are the same in every lane
-        const double h = (hi - lo) / 65.0;
-        const int c = sturm_count(ds, e2, J, lo + h * (double)(lane + 1));
-        const uint64_t bal = __ballot(c > k);
-        const int sstar = bal ? __ffsll((long long)bal) : 65;  // 1-based point
+        if (hi - lo <= tol) break;  // lo, hi are the same in every lane of the group
+        const double h = (hi - lo) / (double)(TPE + 1);
+        const int c = sturm_count(ds, e2, J, lo + h * (double)(s + 1));
+        const uint64_t bal = __ballot(c > k) & gmask;
+        const int sstar = bal ? (__ffsll((long long)bal) - gofs) : TPE + 1;  // 1-based point
         const double nlo = sstar == 1 ? lo : lo + h * (double)(sstar - 1);
-        const double nhi = sstar == 65 ? hi : lo + h * (double)sstar;
+        const double nhi = sstar == TPE + 1 ? hi : lo + h * (double)sstar;
         lo = nlo;
         hi = nhi;
     }
-    if (lane == 0) ho[5 * J + 4 + (J - 1 - k)] = 0.5 * (lo + hi) / sc;
+    if (s == 0) ho[5 * J + 4 + (J - 1 - k)] = 0.5 * (lo + hi) / sc;
 }
 
 __global__ __launch_bounds__(64) void eig_multisect(double* __restrict__ scratch, int J) {
     extern __shared__ double sm[];
-    multisect_one(eig_handoff(scratch, J), J, blockIdx.x, sm);
+    multisect_group<64>(eig_handoff(scratch, J), J, blockIdx.x, true, sm);
 }
 
-// The same for a batch: workgroup w takes eigenvalue w % jmax of problem
-// w / jmax (workgroups beyond that problem's J exit at once).
+// The same for a batch, four eigenvalues per workgroup: workgroup w takes
+// eigenvalues 4 q .. 4 q + 3 of problem w / nq, q = w % nq, nq = ceil(jmax / 4)
+// (groups beyond that problem's J do nothing).
+constexpr int kBatchTpe = 16;
+constexpr int kBatchGroups = 64 / kBatchTpe;
+
 __global__ __launch_bounds__(64) void eig_multisect_batched(const EigArgs* __restrict__ args,
-                                                            int jmax) {
+                                                            int nq) {
     extern __shared__ double sm[];
-    const int p = blockIdx.x / jmax, k = blockIdx.x - p * jmax;
+    const int p = blockIdx.x / nq, q = blockIdx.x - p * nq;
     const int J = args[p].J;
-    if (k >= J) return;  // uniform over the workgroup
-    multisect_one(eig_handoff(args[p].scratch, J), J, k, sm);
+    if (kBatchGroups * q >= J) return;  // uniform over the workgroup
+    const int k = kBatchGroups * q + (int)threadIdx.x / kBatchTpe;
+    multisect_group<kBatchTpe>(eig_handoff(args[p].scratch, J), J, k, k < J, sm);
 }
 
 // One workgroup per problem of a batch.  conditional != 0: only problems whose
@@ -995,8 +1008,9 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
     };
     if (conditional) return launch(eig_batched<128, 0>);
     TK_TRY(launch(eig_batched<128, 1>));
-    hipLaunchKernelGGL(eig_multisect_batched, dim3(count * jmax), dim3(64),
-                       (size_t)2 * jmax * sizeof(double), st, args_dev, jmax);
+    const int nq = (jmax + kBatchGroups - 1) / kBatchGroups;
+    hipLaunchKernelGGL(eig_multisect_batched, dim3(count * nq), dim3(64),
+                       (size_t)2 * jmax * sizeof(double), st, args_dev, nq);
     TK_HIP(hipGetLastError());
     return launch(eig_batched<128, 3>);
 }
