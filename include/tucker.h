@@ -84,9 +84,11 @@ typedef enum tk_gram_precision {
      * is accepted only when the eps threshold lies clear of the tail sums on
      * both sides by a margin of 2^-27 trace R (J - R) / J^2; otherwise that
      * mode's Gram is recomputed in FP64 (tk_tucker.fp64_modes).  There, modes
-     * with J <= 32 whose unfolding has at most 2^26 elements take the FP64
-     * Gram directly: at J <= 32 it costs no more on FP32 data (arithmetic
-     * intensity below the FP64 matrix-core ridge) and needs no guard. */
+     * with J <= 32 whose unfolding has at most 2^26 elements, or whose rows
+     * are runs of L = prod_{k<n} I_k contiguous elements (L a multiple of 8,
+     * at least 64), take the FP64 Gram directly: at J <= 32 it costs no more
+     * on FP32 data (arithmetic intensity below the FP64 matrix-core ridge)
+     * and needs no guard. */
     TK_GRAM_SPLIT_BF16 = 1,
     /* No Gram (sthosvd_compress only; FP64 or FP32 input, dims[n] <=
      * TK_QR_MAX_MODE_DIM at every mode): the singular values of Y_(n) come
