@@ -313,7 +313,7 @@ def algorithmic_bytes(dims, ranks, order, elem):
 
 def combustion256_leg(dev, steps, warmup):
     """The largest single-GPU workload (256x256x256x64x16 stored FP32, 68.7 GB)
-    on the mixed path in mode order 1..5 and 5..1 (Sec. VII: the order sets
+    on the mixed path in mode order 1..5 and 5..1 (Sec. VIII-C: the order sets
     how much data the later modes move)."""
     w = synth.WORKLOADS["combustion256"]
     log(f"[combustion256] generating {w.dims} FP32")
@@ -396,9 +396,9 @@ def time_fixed(x, dims, ranks, order, steps, warmup, gp="fp64", tp="fp64"):
 
 def paper_shapes_leg(dev, steps, warmup):
     """The paper's own workload shapes on this path (FP64, fixed ranks):
-    200^4 -> 20^4 (Sec. VII strong-scaling problem; one node there: ~3 s)
+    200^4 -> 20^4 (Sec. VIII-D strong-scaling problem; one node there: ~3 s)
     and the 25x250x250x250 -> 10x10x100x100 mode-order experiment over all
-    24 orders, with the orders the two greedy heuristics of Sec. VII pick
+    24 orders, with the orders the two greedy heuristics of Sec. VIII-C pick
     and the least-traffic order."""
     out = {}
     dims, ranks = (200, 200, 200, 200), (20, 20, 20, 20)

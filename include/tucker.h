@@ -245,7 +245,7 @@ size_t sthosvd_workspace_bytes(const tk_shape* x, const tk_options* opt);
  * the leading R_n eigenvectors of Y_(n) Y_(n)^T (same eigensolver and sign
  * rule); after mode N the core G = Y x_N U_N^T.  After the ST-HOSVD and
  * after every sweep the fit ||X||^2 - ||G||^2 (the model error
- * ||X - G x {U_n}||^2, Sec. III) is computed in FP64 and read back (one
+ * ||X - G x {U_n}||^2, Sec. II-B) is computed in FP64 and read back (one
  * stream sync per sweep); the iteration stops once a sweep lowers it by at
  * most tol * ||X||^2 (tol >= 0), or after max_sweeps (tol < 0 runs exactly
  * max_sweeps).  Precisions as in opt (fixed ranks: no guard).
@@ -264,7 +264,7 @@ int tucker_hooi(const tk_shape* x, const void* x_dev, const tk_options* opt, int
 
 /* ------------------------------------------------------------ mode order
  * Alg. 1 processes the modes in any order; the order changes the work of
- * the later modes (Sec. VII, mode-order experiment).  Given the extents
+ * the later modes (Sec. VIII-C, mode-order experiment).  Given the extents
  * and the (expected or fixed) ranks, this host-only call writes an order to
  * order_out[0..ndim-1]:
  *   TK_ORDER_GREEDY_FLOPS  at each step the remaining mode with the fewest

@@ -56,8 +56,6 @@ def _load():
         lib = ctypes.CDLL(_LIB_PATH)
         lib.orc_norm2.restype = ctypes.c_double
         lib.orc_norm2.argtypes = [_d, ctypes.c_int64]
-        lib.orc_sum.restype = ctypes.c_double
-        lib.orc_sum.argtypes = [_d, ctypes.c_int64]
         for name in ("orc_unfold", "orc_fold"):
             f = getattr(lib, name)
             f.restype = ctypes.c_int
@@ -322,7 +320,7 @@ def hooi(x, eps: float, ranks=None, order=None, max_sweeps: int = 50,
     Y = X x_m U_m^T over every m != n (ascending m), takes the leading R_n
     eigenvectors of Y_(n) Y_(n)^T as the new U_n, and after mode N forms the
     core G = Y x_N U_N^T.  Stops when the fit ||X||^2 - ||G||^2 (the model
-    error, Sec. III) decreases by at most ``tol * ||X||^2`` in a sweep, or
+    error, Sec. II-B) decreases by at most ``tol * ||X||^2`` in a sweep, or
     after ``max_sweeps`` sweeps; ``tol < 0`` runs exactly ``max_sweeps``."""
     x = _f64_fortran(x)
     init = sthosvd(x, eps, order=order, ranks=ranks)

@@ -57,16 +57,6 @@ static double pw_dot(const double* a, const double* b, int64_t n) {
     return pw_dot(a, b, h) + pw_dot(a + h, b + h, n - h);
 }
 
-static double pw_sum(const double* a, int64_t n) {
-    if (n <= 16) {
-        double s = 0.0;
-        for (int64_t k = 0; k < n; ++k) s += a[k];
-        return s;
-    }
-    int64_t h = n / 2;
-    return pw_sum(a, h) + pw_sum(a + h, n - h);
-}
-
 static double pw_sumsq(const double* a, int64_t n) {
     if (n <= 16) {
         double s = 0.0;
@@ -500,9 +490,6 @@ int orc_error_metrics(const double* x, const double* xh, int64_t count, double* 
     free(d);
     return ORC_OK;
 }
-
-/* Sum of an array (pairwise); exported for the tail-sum and trace checks. */
-double orc_sum(const double* a, int64_t n) { return pw_sum(a, n); }
 
 /* --------------------------------------------- QR-preprocessed SVD (Sec. IX) */
 

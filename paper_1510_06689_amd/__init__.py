@@ -5,8 +5,8 @@ in ``include/tucker.h``.
 The public functions live in :mod:`paper_1510_06689_amd.tucker`; importing
 the package does not load the GPU library.
 """
-from .tucker import (Compressor, TuckerError, TuckerTensor, compression_ratio,  # noqa: F401
-                     error_metrics, gram, library, reconstruct, sthosvd, ttm)
+from .tucker import (Compressor, TuckerError, TuckerTensor, error_metrics, gram,  # noqa: F401
+                     library, reconstruct, sthosvd, ttm)
 
-__all__ = ["Compressor", "TuckerError", "TuckerTensor", "compression_ratio", "error_metrics",
-           "gram", "library", "reconstruct", "sthosvd", "ttm"]
+__all__ = ["Compressor", "TuckerError", "TuckerTensor", "error_metrics", "gram", "library",
+           "reconstruct", "sthosvd", "ttm"]

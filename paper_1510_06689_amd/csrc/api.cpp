@@ -28,7 +28,7 @@ int fail(int status, const char* fmt, ...) {
     return status;
 }
 
-int device_cu_count() { return 256; }
+int device_cu_count() { return 256; }  // MI355X; see tk_common.hpp
 
 int check_shape(const tk_shape* s, const char* what) {
     if (!s) return fail(TK_ERR_INVALID_ARG, "%s: shape is NULL", what);

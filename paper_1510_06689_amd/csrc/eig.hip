@@ -92,6 +92,9 @@ __device__ __forceinline__ double rsq(double s) {
     return fma(0.5 * r, err, r);
 }
 
+// Deterministic start vector entry in [-1, 1) for inverse iteration: the
+// pair (a, b) goes through SplitMix64's golden-ratio increment and its
+// published 64-bit finaliser (Steele, Lea and Flood, 2014).
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
     uint64_t z = ((uint64_t)a << 32) ^ (uint64_t)b ^ 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -123,7 +123,11 @@ __device__ __forceinline__ Tile tile_at(const TileMap& m, int64_t t, int64_t row
 
 // ------------------------------------------------------------- launch
 
-// Number of compute units of the current device (cached per device).
+// Compute units the launch grids are sized for: MI355X's 256, a constant on
+// purpose.  Workspace-size queries are host-only (no HIP call, the same
+// answer with or without a device), and the partial-sum buffers they size
+// follow these grids.  On a part with fewer CUs the grids stay correct, only
+// less evenly spread.
 int device_cu_count();
 
 // Workspace carving: bump allocator over the caller's buffer, 256-B aligned.

@@ -480,7 +480,7 @@ ORDER_RULES = {"flops": 0, "ratio": 1, "bytes": 2}
 def mode_order(dims, ranks, rule: str = "bytes", elem_bytes: int = 4) -> tuple:
     """A mode order for Alg. 1 from the extents and (expected) ranks: the
     greedy least-flops heuristic (``"flops"``), the greedy largest I_n/R_n
-    heuristic (``"ratio"``), both named in Sec. VII's mode-order
+    heuristic (``"ratio"``), both named in Sec. VIII-C's mode-order
     experiment, or the order with the least algorithmic HBM traffic of this
     library (``"bytes"``, exhaustive).  Host-only; no GPU needed."""
     n = len(dims)
@@ -489,11 +489,6 @@ def mode_order(dims, ranks, rule: str = "bytes", elem_bytes: int = 4) -> tuple:
     out = (ctypes.c_int * n)()
     _check(library().sthosvd_mode_order(n, d, r, ORDER_RULES[rule], int(elem_bytes), out))
     return tuple(int(v) for v in out)
-
-
-def compression_ratio(dims, ranks) -> float:
-    """``prod I_n / (prod R_n + sum I_n R_n)`` (Sec. VII-B)."""
-    return math.prod(dims) / (math.prod(ranks) + sum(i * r for i, r in zip(dims, ranks)))
 
 
 class BatchCompressor:

@@ -1,6 +1,6 @@
 """Parity at the largest single-GPU workload, combustion256 (256x256x256x64x16
 stored FP32: 2^34 elements, 68.7 GB), on the mixed path in both mode orders
-(1..5 and 5..1, Sec. VII on the order's cost) and on the FP64-arithmetic path
+(1..5 and 5..1, Sec. VIII-C on the order's cost) and on the FP64-arithmetic path
 over the same FP32 data.
 
 The oracle checks what it can compute one by one: mode-1 Gram entries (J = 256,

@@ -1,4 +1,4 @@
-"""ST-HOSVD in the orders the mode-order rules pick (Sec. VII's experiment,
+"""ST-HOSVD in the orders the mode-order rules pick (Sec. VIII-C's experiment,
 scaled down to 10x50x50x50 of multilinear rank 4x4x20x20) and in the two
 extreme orders, with fixed ranks, against the FP64 oracle run in the same
 order: same subspaces, same discarded energy, the identity

@@ -1,6 +1,6 @@
 """Mode-order rules of sthosvd_mode_order (host-only C-ABI call, no GPU).
 
-Pins: Sec. VII's mode-order experiment (25x250x250x250 tensor of multilinear
+Pins: Sec. VIII-C's mode-order experiment (25x250x250x250 tensor of multilinear
 rank 10x10x100x100) states that the greedy least-flops heuristic does not
 find the best order there and that the best order starts with the second
 mode, the one with the largest compression ratio; the byte rule is checked

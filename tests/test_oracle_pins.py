@@ -389,6 +389,43 @@ def test_compression_ratio_table2():
         assert round(c) == printed, (name, c)
 
 
+def test_error_metrics_hand_cases():
+    """Table II's two error columns on hand-worked tensors (all values exact
+    in binary).  The largest deviation is negative (X~ above X), sits away
+    from the largest |X| and from the largest |X~|, and in the later cases at
+    the first and at the last element, so a missing absolute value, a maximum
+    taken over X or X~ instead of X - X~, a signed maximum or a loop that
+    skips an end element each give a different max-abs value."""
+    # 2 x 2 x 2, Fortran order: element k of the flat array is offset k
+    x = np.asfortranarray(np.array([5.0, -1.0, 2.0, 0.5, -3.0, 0.25, 1.5, 0.0])
+                          .reshape((2, 2, 2), order="F"))
+    xh = np.asfortranarray(np.array([4.75, -1.0, 2.75, 0.5, -3.0, 0.0, 1.5, 0.125])
+                           .reshape((2, 2, 2), order="F"))
+    e2, mx, n2 = oracle.error_metrics(x, xh)
+    # X - X~ = [0.25, 0, -0.75, 0, 0, 0.25, 0, -0.125]
+    assert mx == 0.75
+    assert e2 == 0.0625 + 0.5625 + 0.0625 + 0.015625
+    assert n2 == 25.0 + 1.0 + 4.0 + 0.25 + 9.0 + 0.0625 + 2.25
+    # largest deviation at the first element, negative; |X| largest elsewhere
+    a = np.array([1.0, 8.0, -2.0, 0.5, 0.0, -0.5])
+    b = np.array([2.5, 8.0, -2.0, 0.25, -0.5, 0.0])
+    e2, mx, n2 = oracle.error_metrics(np.asfortranarray(a.reshape(2, 3, order="F")),
+                                      np.asfortranarray(b.reshape(2, 3, order="F")))
+    assert (mx, e2, n2) == (1.5, 2.25 + 0.0625 + 0.25 + 0.25, 1.0 + 64.0 + 4.0 + 0.25 + 0.25)
+    # largest deviation at the last element, negative
+    a = np.array([3.0, -4.0, 0.0, 1.0])
+    b = np.array([3.0, -4.0, 0.5, 3.0])
+    e2, mx, n2 = oracle.error_metrics(np.asfortranarray(a.reshape(2, 2, order="F")),
+                                      np.asfortranarray(b.reshape(2, 2, order="F")))
+    assert (mx, e2, n2) == (2.0, 0.25 + 4.0, 9.0 + 16.0 + 1.0)
+    # X~ = X gives zero error; the metrics are symmetric only in the first two
+    e2, mx, n2 = oracle.error_metrics(x, x)
+    assert (e2, mx) == (0.0, 0.0)
+    e2b, mxb, n2b = oracle.error_metrics(xh, x)
+    e2a, mxa, _ = oracle.error_metrics(x, xh)
+    assert (e2b, mxb) == (e2a, mxa) and n2b == float(np.sum(xh * xh))
+
+
 def test_synthetic_generator_contract():
     """The generator's planted part has exactly the requested multilinear
     rank and the noise has the requested relative size."""
