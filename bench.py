@@ -74,21 +74,75 @@ def time_gram(x, mode, precision, reps, stream):
     return start.elapsed_time(end) / 1e3 / reps
 
 
-def cpu_baseline(x_dev, eps, path):
-    """The FP64 CPU oracle on a three-time-step slab of the same tensor."""
+def host_info():
+    """The host the run is on: logical CPUs, CPU model, memory."""
+    info = {"host_cores": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["host_cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["host_ram_gb"] = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+SLAB_STEPS = 8   # time steps of the oracle's slab: 128x128x128x32x8, 2 GB in FP32
+
+
+def slab_check(x64, x32, eps):
+    """The FP64 CPU oracle (single-threaded, as it stands) on a slab of the
+    bench tensor -- its first SLAB_STEPS time steps, stored FP32 as on the
+    mixed path -- timed as the CPU baseline, and both GPU paths run on the
+    same slab: ranks against the oracle's, discarded sums and relative errors
+    against the oracle's (its error from the pinned ST-HOSVD identity
+    ||X - X~||^2 = sum of discarded eigenvalues)."""
     import oracle
     import numpy as np
-    sample = x_dev[..., 0:3]
-    xs = np.asfortranarray(sample.double().cpu().numpy())
+    s32 = x32[..., 0:SLAB_STEPS]
+    xs = np.asfortranarray(s32.double().cpu().numpy())
     t0 = time.perf_counter()
-    oracle.sthosvd(xs, eps)
+    ref = oracle.sthosvd(xs, eps)
     dt = time.perf_counter() - t0
-    in_bytes = xs.size * x_dev.element_size()
-    return {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"three time steps of the same tensor, dims {list(xs.shape)}, "
-                      f"{in_bytes} bytes as stored on the {path} path, {dt:.1f} s "
-                      f"single-threaded"}
+    del xs
+    rel_ref = math.sqrt(sum(ref.discarded) / ref.norm2)
+    tau = eps * eps * ref.norm2 / len(ref.ranks)
+    out = {"slab_dims": list(s32.shape), "eps": eps, "oracle_ranks": list(ref.ranks),
+           "oracle_relerr": rel_ref, "oracle_seconds": round(dt, 2)}
+    legs = (("fp64", x64[..., 0:SLAB_STEPS] if x64 is not None else None, "fp64", "fp64"),
+            ("mixed", s32, "split_bf16", "bf16x3"))
+    for name, xs_dev, gp, tp in legs:
+        if xs_dev is None:
+            continue
+        r = tucker.sthosvd(xs_dev, eps, gram_precision=gp, ttm_precision=tp)
+        xh = tucker.reconstruct(r.core, r.factors)
+        e2, _, n2 = tucker.error_metrics(xs_dev, xh)
+        del xh
+        rel = math.sqrt(e2 / n2)
+        out[name] = {"ranks": list(r.ranks), "ranks_equal_oracle": r.ranks == ref.ranks,
+                     "relerr": rel, "abs_delta_relerr_vs_oracle": abs(rel - rel_ref),
+                     "max_abs_delta_discarded_over_tau":
+                         max(abs(a - b) for a, b in zip(r.discarded, ref.discarded)) / tau,
+                     "tail_error_bound_over_tau": [b / tau for b in r.tail_error_bound],
+                     "fp64_modes": list(r.fp64_modes), "ttm_precision_used": r.ttm_precision,
+                     "storage": str(xs_dev.dtype).replace("torch.", "")}
+        log(f"[slab] {name}: ranks {r.ranks} (oracle {ref.ranks}), relerr {rel:.6e} "
+            f"(oracle {rel_ref:.6e})")
+    torch.cuda.empty_cache()
+    in_bytes = s32.numel() * s32.element_size()
+    cpu = {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"first {SLAB_STEPS} time steps of the same tensor, dims "
+                     f"{list(s32.shape)}, {in_bytes} bytes stored FP32 (the mixed path's "
+                     f"input), eps {eps}, {dt:.1f} s single-threaded"}
+    cpu.update(host_info())
+    return cpu, out
 
 
 def measured_traffic(name):
@@ -154,7 +208,10 @@ def run_leg(name, x, w, gp, tp, steps, warmup):
            "algorithmic_bytes": alg, "algorithmic_gbs": round(alg / (ms / 1e3) / 1e9, 1),
            "ranks": list(res.ranks),
            "relerr": math.sqrt(e2 / n2), "max_abs_err": mx, "gram": gp, "ttm": tp,
-           "storage": str(x.dtype).replace("torch.", "")}
+           "storage": str(x.dtype).replace("torch.", ""), "fp64_modes": list(res.fp64_modes),
+           "ttm_precision_used": res.ttm_precision,
+           "tail_error_bound_over_tau": [b / (w.eps ** 2 * res.norm2 / len(w.dims)) if w.eps > 0
+                                         else 0.0 for b in res.tail_error_bound]}
     log(f"[{name}] {steps} steps: {ms:.3f} ms/step, {leg['input_gbs']} GB/s, ranks {res.ranks},"
         f" relerr {leg['relerr']:.3e}")
     return leg, res
@@ -220,6 +277,56 @@ def qr_leg(x, w, steps, warmup, stream, eps=1e-5):
     log(f"[qr] eps {eps}: qr {out['qr']['ms_per_step']} ms ranks {out['qr']['ranks']}, "
         f"fp64 gram {out['fp64_gram']['ms_per_step']} ms ranks {out['fp64_gram']['ranks']}; "
         f"mode-1 TSQR {t * 1e3:.2f} ms = {fl / t / 1e12:.2f} TFLOP/s")
+    return out
+
+
+def config3_leg(x32, w, steps, warmup):
+    """The precision configuration: the same tensor stored FP32 at eps 1e-3
+    and 1e-5; split-bf16 Gram with split-bf16 TTM, and with the bf16 TTM the
+    configuration names (under the eps rule raised where its error would
+    reach the threshold); each against the FP64-arithmetic path on the same
+    FP32 data (ranks, relative error, discarded sums).  With that path's
+    ranks fixed the bf16 TTM runs as requested and its error is stated."""
+    import dataclasses
+    out = {}
+    for eps in (1e-3, 1e-5):
+        we = dataclasses.replace(w, eps=eps)
+        block = {}
+        legs = (("fp64_reference", "fp64", "fp64", None),
+                ("split_gram_bf16x3_ttm", "split_bf16", "bf16x3", None),
+                ("split_gram_bf16_ttm", "split_bf16", "bf16", None))
+        ref = None
+        for name, gp, tp, ranks in legs:
+            leg, res = run_leg(f"config3 eps={eps} {name}", x32, we, gp, tp, steps, warmup)
+            if ref is None:
+                ref = (leg, res)
+            else:
+                tau = eps * eps * res.norm2 / len(w.dims)
+                leg["ranks_equal_reference"] = leg["ranks"] == ref[0]["ranks"]
+                leg["abs_delta_relerr_vs_reference"] = abs(leg["relerr"] - ref[0]["relerr"])
+                leg["max_abs_delta_discarded_over_tau"] = max(
+                    abs(a - b) for a, b in zip(res.discarded, ref[1].discarded)) / tau
+                leg["speedup_vs_reference"] = round(ref[0]["ms_per_step"] / leg["ms_per_step"], 3)
+            block[name] = leg
+        comp = tucker.Compressor(w.dims, x32.dtype, x32.device, 0.0, ranks=ref[1].ranks,
+                                 gram_precision="split_bf16", ttm_precision="bf16")
+        comp.run(x32)
+        r = comp.result(copy=True)
+        del comp
+        xh = tucker.reconstruct(r.core, r.factors)
+        e2, mx, n2 = tucker.error_metrics(x32, xh)
+        del xh
+        torch.cuda.empty_cache()
+        rel = math.sqrt(e2 / n2)
+        block["bf16_ttm_fixed_ranks"] = {
+            "ranks": list(r.ranks), "ttm_precision_used": r.ttm_precision, "relerr": rel,
+            "abs_delta_relerr_vs_reference": abs(rel - ref[0]["relerr"]), "max_abs_err": mx,
+            "note": "ranks fixed to the FP64 reference's; the bf16 TTM's own error"}
+        log(f"[config3] eps {eps}: bf16 TTM with fixed ranks relerr {rel:.4e} "
+            f"(reference {ref[0]['relerr']:.4e})")
+        out[f"eps={eps:g}"] = block
+    out["workload"] = ("combustion128 stored FP32 (8.6 GB), eps 1e-3 and 1e-5, modes 1..5; "
+                       "reference: FP64 Gram and FP64-arithmetic TTM on the same FP32 data")
     return out
 
 
@@ -362,6 +469,17 @@ def paper_flops(dims, ranks, order):
     return total
 
 
+def symmetric_flops(dims, ranks, order):
+    """The least flops the method needs: symmetric Gram (J_n + 1) #Y_n and
+    TTM 2 R_n #Y_n per mode."""
+    cur, total = list(dims), 0
+    for n in order:
+        ny = math.prod(cur)
+        total += (dims[n] + 1 + 2 * ranks[n]) * ny
+        cur[n] = ranks[n]
+    return total
+
+
 def hooi_sweep_flops(dims, ranks):
     """One HOOI sweep by the paper's counts: per mode n, the TTMs with every
     U_m^T (m != n, ascending; 2 R_m #Y each) and the Gram (2 I_n #Y_n), then
@@ -407,8 +525,12 @@ def paper_shapes_leg(dev, steps, warmup):
     torch.cuda.synchronize()
     ms, got = time_fixed(x, dims, ranks, tuple(range(4)), steps, warmup)
     fl = paper_flops(dims, ranks, range(4))
+    fl_sym = symmetric_flops(dims, ranks, range(4))
     out["200^4->20^4"] = {"ms": round(ms, 3), "gflops_paper_count": round(fl / ms / 1e6, 1),
                           "frac_fp64_peak": round(fl / ms / 1e9 / FP64_MFMA_PEAK_TFS, 4),
+                          "gflops_symmetric_count": round(fl_sym / ms / 1e6, 1),
+                          "frac_fp64_peak_symmetric_count":
+                              round(fl_sym / ms / 1e9 / FP64_MFMA_PEAK_TFS, 4),
                           "input_gbs": round(x.numel() * 8 / ms / 1e6, 1), "ranks": list(got),
                           "paper_one_node_s": 3.0}
     log(f"[paper] 200^4 -> 20^4 FP64: {ms:.2f} ms, {fl / ms / 1e6:.0f} GFLOP/s (paper's counts)")
@@ -468,6 +590,8 @@ def main():
                     help="skip the 68.7 GB combustion256 leg (mode orders 1..5 and 5..1)")
     ap.add_argument("--no-qr", action="store_true",
                     help="skip the QR-preprocessed SVD leg (Sec. IX) at eps 1e-5")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the precision configuration (FP32 tensor at eps 1e-3 and 1e-5)")
     ap.add_argument("--gram-reps", type=int, default=10)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="counter runs: only the mode-1 split Gram and TTM of the FP32 tensor "
@@ -554,9 +678,11 @@ def main():
             "abs_delta": abs(legs["fp64"]["relerr"] - legs["mixed"]["relerr"])}
     if qr_out is not None:
         out["qr_svd"] = qr_out
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(x, w.eps, head)
+    if x32 is not None and not args.no_config3:
+        out["config3"] = config3_leg(x32, w, max(1, args.steps // 4), 1)
+    if x32 is not None and not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a slab) and the GPU paths on the same slab ...")
+        out["cpu_baseline"], out["oracle_slab"] = slab_check(x64, x32, w.eps)
     if not args.no_batch:
         x = x64 = x32 = None
         torch.cuda.empty_cache()

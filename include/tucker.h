@@ -75,15 +75,21 @@ typedef enum tk_gram_precision {
      * widened exactly). */
     TK_GRAM_FP64 = 0,
     /* FP32 input only.  Per column tile and row i with max |x| < 2^E_i, each
-     * value is split as hi = round(x 2^(7-E_i)) (an integer, exact in bf16)
-     * and lo = bf16(x 2^(7-E_i) - hi); the four products hh, hl, lh, ll run
-     * on bf16 matrix cores.  hh is summed exactly in FP32, the other three in
-     * a second FP32 accumulator; both are scaled by 2^(E_i+E_j-14) and added
-     * into FP64 after every tile.  Each element is represented to 2^-16 of
-     * its row's maximum.  In sthosvd_compress a rank found from such a Gram
-     * is accepted only when the eps threshold lies clear of the tail sums on
-     * both sides by a margin of 2^-27 trace R (J - R) / J^2; otherwise that
-     * mode's Gram is recomputed in FP64 (tk_tucker.fp64_modes).  There, modes
+     * value's s = x 2^(7-E_i) is rounded to the grid 2^-8 (16-bit fixed
+     * point) and split into hi = round(s) and lo = round(256 (s - hi)) / 256,
+     * both 8-bit integers up to scale and exact in bf16; the four products
+     * hh, hl, lh, ll run on bf16 matrix cores into three FP32 accumulators
+     * (hh; hl + lh; ll) whose sums over a tile are exact, scaled by
+     * 2^(E_i+E_j-14) and added into FP64 after every tile.  Each element is
+     * represented to 2^-16 of 2^E_i.  The quantization error d of every
+     * element is formed exactly, and sum_k d_ik^2 is subtracted from S_ii:
+     * quantization noise independent of the data adds its energy to the
+     * Gram's diagonal, which would raise its trailing eigenvalue sums by
+     * about ||D||_F^2 (J-R)/J, in later modes close to the rank threshold.  In
+     * sthosvd_compress a rank found from such a Gram is accepted only when
+     * the eps threshold lies clear of the tail sums by the bound of
+     * tk_tucker.tail_error_bound; otherwise that mode's Gram is recomputed
+     * in FP64 (tk_tucker.fp64_modes).  There, modes
      * with J <= 32 whose unfolding has at most 2^26 elements, or whose rows
      * are runs of L = prod_{k<n} I_k contiguous elements (L a multiple of 8,
      * at least 64), take the FP64 Gram directly: at J <= 32 it costs no more
@@ -111,7 +117,8 @@ typedef enum tk_gram_precision {
  * there and meets every option's error bound. */
 typedef enum tk_ttm_precision {
     TK_TTM_FP64 = 0,   /* FP64 products and accumulation (FP64 or FP32 storage) */
-    TK_TTM_BF16 = 1,   /* FP32 storage: operands rounded to bf16, FP32 accumulation */
+    TK_TTM_BF16 = 1,   /* FP32 storage: operands rounded to bf16, FP32 accumulation
+                          (relative error ~2^-8); see tk_tucker.ttm_precision_used */
     TK_TTM_BF16X3 = 2  /* FP32 storage: hi = bf16(x), lo = bf16(x - hi) on both operands,
                           products hh + hl + lh, FP32 accumulation (relative error ~2^-17);
                           see tk_tucker.ttm_precision_used for its use in sthosvd_compress */
@@ -210,22 +217,47 @@ typedef struct tk_tucker {
                                           descending, mode n at offset sum_{m<n} I_m; may be NULL */
     /* host outputs, written before sthosvd_compress returns TK_OK */
     int64_t ranks[TK_MAX_NDIM];        /* R_n */
-    double discarded[TK_MAX_NDIM];     /* sum_{r > R_n} lambda_r at mode n */
+    double discarded[TK_MAX_NDIM];     /* sum_{r > R_n} lambda_r at mode n (at least 0) */
     double norm2;                      /* ||X||^2 */
     uint32_t fp64_modes;               /* bit n: mode n's Gram was recomputed in FP64 because
                                           the split-bf16 Gram could not certify its rank
                                           (gram_precision TK_GRAM_SPLIT_BF16 only) */
-    int32_t ttm_precision_used;        /* tk_ttm_precision the TTMs ran in: TK_TTM_BF16X3
-                                          becomes TK_TTM_FP64 under the eps rule when
-                                          eps^2 / N < 2^-31, where its 2^-17 relative output
-                                          error would reach the rank threshold */
+    int32_t ttm_precision_used;        /* tk_ttm_precision the TTMs ran in.  Under the eps
+                                          rule a precision whose relative output error would
+                                          reach the rank threshold is raised: TK_TTM_BF16
+                                          (~2^-8) becomes TK_TTM_BF16X3 when
+                                          eps^2 / N < 2^-13, and TK_TTM_BF16X3 (~2^-17)
+                                          becomes TK_TTM_FP64 when eps^2 / N < 2^-31.
+                                          Fixed ranks keep the requested precision. */
+    double tail_error_bound[TK_MAX_NDIM]; /* when mode n's Gram ran split-bf16: a bound on
+                                          |discarded[n] - t|, t the tail sum of the exact
+                                          Gram of the same Y_n: ||D||_F^2 / 8 (the
+                                          subtracted diagonal of D D^T, trusted to an
+                                          eighth of its size) plus 6 standard deviations
+                                          sqrt(4 delta^2 t + 2 K delta^4 (J - R)) of the
+                                          remaining error (the split Gram subtracts
+                                          diag(D D^T) exactly; the cross terms Y D^T +
+                                          D Y^T and the off-diagonal of D D^T have mean 0
+                                          when the quantization errors are modelled as
+                                          independent of the data and of each other,
+                                          |d| <= 2^(E_max - 16), variance <= delta^2 =
+                                          4^(E_max - 16) / 3; K columns, J rows, rank R).
+                                          0 for FP64 Grams.  Under the eps rule a
+                                          split-bf16 rank is accepted only when
+                                          eps^2 ||X||^2 / N exceeds discarded[n] by this
+                                          bound and falls short of the next larger tail sum
+                                          by the same bound taken there; otherwise the mode
+                                          is redone in FP64. */
 } tk_tucker;
 
 /*
  * Alg. 1 (ST-HOSVD).  For each mode n in opt->mode_order: S = Y_(n) Y_(n)^T;
  * eigendecomposition of S in FP64; R_n = min R >= 1 with
  * sum_{r>R} lambda_r(S) <= eps^2 ||X||^2 / N (||X|| of the input, N = ndim,
- * negative rounding eigenvalues counted as 0); U_n = the leading R_n
+ * negative rounding eigenvalues counted as 0 -- for a split-bf16 Gram the
+ * raw eigenvalues: subtracting its quantization energy leaves small negative
+ * ones in noise-level directions, and their raw sum estimates the exact
+ * tail); U_n = the leading R_n
  * eigenvectors (each signed so that its largest-magnitude entry is
  * positive); Y <- Y x_n U_n^T.  The final Y is the core G.
  *   x, x_dev    input tensor (not modified).
@@ -334,9 +366,12 @@ size_t error_metrics_workspace_bytes(const tk_shape* x);
  * into a HIP graph once and replayed.
  *
  * Requirements: TK_F32 storage, gram_precision TK_GRAM_SPLIT_BF16,
- * ttm_precision TK_TTM_BF16X3 or TK_TTM_BF16 (TK_TTM_BF16X3 needs
- * eps^2/N >= 2^-31 under the eps rule), every problem with the same ndim and
- * mode order, every extent <= 128.
+ * ttm_precision TK_TTM_BF16X3 or TK_TTM_BF16; under the eps rule the TTM's
+ * error must stay below the rank threshold as in sthosvd_compress
+ * (TK_TTM_BF16X3 needs eps^2/N >= 2^-31, TK_TTM_BF16 eps^2/N >= 2^-13;
+ * otherwise TK_ERR_UNSUPPORTED: a batch does not change the precision it
+ * was given), every problem with the same ndim and mode order, every
+ * extent <= 128.
  *
  * A mode whose rank the split Gram could not certify (the guard of
  * TK_GRAM_SPLIT_BF16) is recomputed on the device within the same run, as in
@@ -356,6 +391,9 @@ typedef struct tk_batch_outputs {
                                        bit 2 = rank not yet certified (cleared by the
                                        FP64 recomputation within the run);
                                        [1] bit n = mode n recomputed in FP64 */
+    double* tail_bound_dev;         /* device [batch * ndim] or NULL: per problem and mode,
+                                       the bound of tk_tucker.tail_error_bound (0 where the
+                                       mode was recomputed in FP64) */
 } tk_batch_outputs;
 
 /* Work partition: column tiles per Gram workgroup and 16-column blocks per

@@ -66,7 +66,8 @@ static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 using namespace tk;
 
 // Scalar block of one compression (device): [0] ||X||^2, [1..8] discarded
-// sums, [16..23] ranks, [32] status flags.  The per-mode readback copies
+// sums, [16..23] ranks, [32] status flags, [40..41] split statistics of the
+// last split-bf16 Gram, [48..55] tail-sum error bounds.  The per-mode readback copies
 // its first 33 doubles in one transfer into pinned host memory allocated
 // once per thread (kept for the thread's lifetime: 512 bytes); pageable
 // stack memory is the fallback if that allocation fails.
@@ -358,7 +359,6 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
             return fail(TK_ERR_INVALID_ARG, "sthosvd_compress: factors_dev[%d] NULL", n);
     TK_TRY(check_ws(ws, ws_bytes, pl.total, "sthosvd_compress"));
     hipStream_t st = (hipStream_t)stream;
-    const size_t b = dtype_size(x->dtype);
 
     Carver c(ws, ws_bytes);
     void* ybuf[2] = {c.take(pl.y_bytes[0]), c.take(pl.y_bytes[1])};
@@ -375,6 +375,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     double* disc_dev = scal + 1;                 // [1..8]
     int64_t* rank_dev = (int64_t*)(scal + 16);   // [16..23]
     int* flags_dev = (int*)(scal + 32);          // [32]
+    double* stats_dev = scal + 40;               // [40..41]
+    double* bound_dev = scal + 48;               // [48..55]
     double* lam_all = out->eigvals_dev ? out->eigvals_dev : lam_ws;
 
     TK_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(double), st));
@@ -392,9 +394,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     const void* ycur = x_dev;
     const double eps2n = opt->eps * opt->eps / (double)N;
     uint32_t fp64_modes = 0;
-    int ttm_prec = opt->ttm_precision;
-    if (ttm_prec == TK_TTM_BF16X3 && !opt->fixed_ranks && eps2n < kSplitTtmFloor)
-        ttm_prec = TK_TTM_FP64;
+    const int ttm_prec = opt->fixed_ranks ? opt->ttm_precision
+                                          : ttm_precision_for_eps(opt->ttm_precision, eps2n);
     double nu_host = 0.0;
 
     for (int s = 0; s < N; ++s) {
@@ -414,7 +415,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
             TK_TRY(launch_jw(r_ws, v.J, S, st));
         } else {
             TK_TRY(launch_gram(ycur, x->dtype, v, gprec, S, s == 0 ? nu_dev : nullptr, gram_ws,
-                               pl.gram_bytes, st));
+                               pl.gram_bytes, st,
+                               gprec == TK_GRAM_SPLIT_BF16 ? stats_dev : nullptr));
         }
         EigArgs ea;
         ea.s = S;
@@ -431,7 +433,12 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         ea.flags = flags_dev;
         ea.scratch = eig_ws;
         const bool mixed = gprec == TK_GRAM_SPLIT_BF16;
-        ea.guard = (mixed && !opt->fixed_ranks) ? kSplitGramGuard : 0.0;
+        // split Gram: bound the tail-sum error (and, under the eps rule,
+        // certify the rank) from its measured representation error
+        ea.guard = mixed ? kSplitGramGuard : 0.0;
+        ea.split_stats = mixed ? stats_dev : nullptr;
+        ea.ncols = (double)v.L * (double)v.B;
+        ea.tail_bound = bound_dev + n;
         TK_TRY(launch_eig(ea, st));
         if (qr) TK_TRY(launch_jw_extract(z_ws, v.J, (int)pl.cap[n], rank_dev + n,
                                          out->factors_dev[n], st));
@@ -451,7 +458,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
                 TK_HIP(hipMemsetAsync(flags_dev, 0, sizeof(int), st));
                 TK_TRY(launch_gram(ycur, x->dtype, v, TK_GRAM_FP64, S, s == 0 ? nu_dev : nullptr,
                                    gram_ws, pl.gram_bytes, st));
-                ea.guard = 0.0;
+                ea.guard = 0.0;  // an FP64 Gram: plain rank rule
+                ea.split_stats = nullptr;
                 TK_TRY(launch_eig(ea, st));
                 TK_TRY(read_scalars(scal, st, n, &rk, &nu_read, &flags));
                 fp64_modes |= 1u << n;
@@ -482,9 +490,10 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         memcpy(cur, nxt, sizeof cur);
         ycur = dst;
     }
-    double disc[TK_MAX_NDIM];
+    double disc[TK_MAX_NDIM], bounds[TK_MAX_NDIM];
     int flags = 0;
     TK_HIP(hipMemcpyAsync(disc, disc_dev, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    TK_HIP(hipMemcpyAsync(bounds, bound_dev, N * sizeof(double), hipMemcpyDeviceToHost, st));
     TK_HIP(hipMemcpyAsync(&nu_host, nu_dev, sizeof(double), hipMemcpyDeviceToHost, st));
     TK_HIP(hipMemcpyAsync(&flags, flags_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TK_HIP(hipStreamSynchronize(st));
@@ -494,6 +503,7 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     for (int n = 0; n < N; ++n) {
         out->ranks[n] = cur[n];
         out->discarded[n] = disc[n];
+        out->tail_error_bound[n] = bounds[n];
     }
     out->norm2 = nu_host;
     out->fp64_modes = fp64_modes;

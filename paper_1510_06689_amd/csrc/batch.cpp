@@ -73,6 +73,7 @@ struct tk_batch {
     double* disc_dev = nullptr;
     double* norm2_dev = nullptr;
     int32_t* status_dev = nullptr;
+    double* tail_bound_dev = nullptr;  // optional output
     std::vector<StepPlan> steps;
     char* tables_dev = nullptr;
     std::vector<double*> lam;  // per problem, sum of extents
@@ -104,9 +105,12 @@ int check_batch(int batch, const tk_shape* shapes, const tk_options* opt) {
         return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: needs gram_precision TK_GRAM_SPLIT_BF16");
     if (opt->ttm_precision != TK_TTM_BF16X3 && opt->ttm_precision != TK_TTM_BF16)
         return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: needs a bf16 TTM precision");
-    if (opt->ttm_precision == TK_TTM_BF16X3 && !opt->fixed_ranks &&
-        opt->eps * opt->eps / N < kSplitTtmFloor)
-        return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: eps below the split TTM's accuracy");
+    if (!opt->fixed_ranks &&
+        ttm_precision_for_eps(opt->ttm_precision, opt->eps * opt->eps / N) != opt->ttm_precision)
+        return fail(TK_ERR_UNSUPPORTED, "sthosvd_batch: eps^2/N below the %s TTM's accuracy "
+                    "floor (%s)", opt->ttm_precision == TK_TTM_BF16 ? "bf16" : "split-bf16",
+                    opt->ttm_precision == TK_TTM_BF16 ? "2^-13; use TK_TTM_BF16X3"
+                                                      : "2^-31");
     bool seen[TK_MAX_NDIM] = {false};
     for (int k = 0; k < N; ++k) {
         const int n = opt->mode_order ? opt->mode_order[k] : k;
@@ -143,7 +147,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
     // per-problem buffers
     struct Bufs {
         void* y[2];
-        double *partial, *S, *scratch, *lam;
+        double *partial, *aux, *stats, *S, *scratch, *lam;
         int* nparts;
     };
     std::vector<Bufs> bufs(B);
@@ -151,7 +155,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         const tk_shape& sh = shapes[b];
         int64_t capcur[TK_MAX_NDIM];
         for (int k = 0; k < N; ++k) capcur[k] = sh.dims[k];
-        size_t yb[2] = {0, 0}, pb = 0;
+        size_t yb[2] = {0, 0}, pb = 0, ab = 0;
         int jmax = 1;
         for (int s = 0; s < N; ++s) {
             const int n = order[s];
@@ -162,6 +166,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
                                                                : kDefaultGramTilesPerWg;
             const int nwg = std::max(1, std::min(4096, ceil_div(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw)));
             pb = std::max(pb, (size_t)nwg * np16 * 256 * sizeof(double));
+            ab = std::max(ab, (size_t)nwg * 2 * sizeof(double));
             jmax = std::max(jmax, v.J);
             capcur[n] = cap_of(sh, opt, n);
             if (s + 1 < N) {
@@ -175,6 +180,8 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         bufs[b].y[0] = c.take(yb[0]);
         bufs[b].y[1] = c.take(yb[1]);
         bufs[b].partial = (double*)c.take(pb);
+        bufs[b].aux = (double*)c.take(ab);
+        bufs[b].stats = (double*)c.take(2 * sizeof(double));
         bufs[b].S = (double*)c.take((size_t)jmax * jmax * sizeof(double));
         bufs[b].scratch = (double*)c.take(eig_scratch_doubles(jmax) * sizeof(double));
         bufs[b].lam = (double*)c.take((size_t)sumd * sizeof(double));
@@ -221,14 +228,16 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             bv.done = done;
             const void* yin = s == 0 ? (h ? h->x[b] : nullptr) : bufs[b].y[(s - 1) & 1];
             const int* status = h ? h->status_dev + 2 * b : nullptr;
-            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial, status, bufs[b].nparts,
-                             ceil_div(ntiles, nwg)};
+            BatchGramTask gt{bv, (const float*)yin, bufs[b].partial, bufs[b].aux, status,
+                             bufs[b].nparts, ceil_div(ntiles, nwg)};
             gt.v.nwg = nwg;
             gclass[jb].push_back(gt);
             BatchReduceTask rt{bufs[b].partial, bufs[b].S,
-                               s == 0 && h ? h->norm2_dev + b : nullptr, nwg, np16, nb16, v.J, 0, 0,
-                               status, bufs[b].nparts};
-            rt.nwg = ceil_div((int64_t)np16 * 256, 64) + (s == 0 ? 1 : 0);
+                               s == 0 && h ? h->norm2_dev + b : nullptr, bufs[b].aux,
+                               bufs[b].stats, nwg, np16, nb16, v.J, 0, 0, status,
+                               bufs[b].nparts};
+            // one more workgroup: split statistics, and at step 0 the trace
+            rt.nwg = ceil_div((int64_t)np16 * 256, 64) + 1;
             rt.wg_begin = red_wg;
             red_wg += rt.nwg;
             red.push_back(rt);
@@ -247,7 +256,11 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             ea.disc_out = h ? h->disc_dev + (size_t)b * N + n : nullptr;
             ea.flags = h ? h->status_dev + 2 * b : nullptr;
             ea.scratch = bufs[b].scratch;
-            ea.guard = opt->fixed_ranks ? 0.0 : kSplitGramGuard;
+            ea.guard = kSplitGramGuard;  // the rank rule flags only under the eps rule
+            ea.split_stats = bufs[b].stats;
+            ea.ncols = (double)v.L * (double)v.B;  // at the capacity shape: an upper bound
+            ea.tail_bound = h && h->tail_bound_dev ? h->tail_bound_dev + (size_t)b * N + n
+                                                    : nullptr;
             sp.jmax = std::max(sp.jmax, v.J);
             // TTM into the other buffer (the core at the last step)
             void* yout = s + 1 == N ? (h ? h->cores[b] : nullptr) : bufs[b].y[s & 1];
@@ -360,6 +373,7 @@ int sthosvd_batch_create(int batch, const tk_shape* shapes, const void* const* x
     h->disc_dev = out->discarded_dev;
     h->norm2_dev = out->norm2_dev;
     h->status_dev = out->status_dev;
+    h->tail_bound_dev = out->tail_bound_dev;
     std::vector<char> tables;
     plan_batch(batch, shapes, &h->opt, tuning, ws, h, &tables);
     hipStream_t st = (hipStream_t)stream;

@@ -621,8 +621,13 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     (void)sc;
     // Jordan-Wielandt input: the leading half of the spectrum is sigma(R)
     const int Jv = a.aug ? J / 2 : J;
+    // Tail sums: negative rounding eigenvalues count as 0 -- except for a
+    // split Gram, whose subtracted quantization energy leaves small negative
+    // eigenvalues in noise-level directions; there the raw sum is the
+    // estimate of the exact tail (clamping would raise it).
+    const bool raw = a.guard > 0.0 && a.split_stats != nullptr && !a.aug;
     auto val = [&](int r) {
-        const double l = fmax(lam[r], 0.0);
+        const double l = raw ? lam[r] : fmax(lam[r], 0.0);
         return a.aug ? l * l : l;
     };
     for (int i = tid; i < Jv; i += kEigThreads) a.lambda[i] = a.aug ? val(i) : lam[i];
@@ -631,35 +636,46 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     if (tid == 0) {
         int R;
         double tail = 0.0;
-        if (a.fixed_rank > 0) {
+        const bool eps_rule = a.fixed_rank <= 0;
+        const double tau = eps_rule ? a.eps2_over_n * (*a.nu) : 0.0;
+        if (!eps_rule) {
             R = a.fixed_rank < Jv ? a.fixed_rank : Jv;
             for (int r = Jv - 1; r >= R; --r) tail += val(r);
         } else {
-            const double tau = a.eps2_over_n * (*a.nu);
             R = Jv;
             while (R > 1 && tail + val(R - 1) <= tau) {
                 tail += val(R - 1);
                 --R;
             }
-            if (a.guard > 0.0) {
-                // the decision must survive the Gram's error in the tail
-                // sums: tau - t_R and t_{R-1} - tau both beyond the margin
-                double tr = 0.0;
-                for (int r = J - 1; r >= 0; --r) tr += fmax(lam[r], 0.0);
-                const double margin = a.guard * tr * (double)R * (double)(J - R) /
-                                      ((double)J * (double)J);
-                const double next = tail + fmax(lam[R - 1], 0.0);
-                if (tau - tail < margin || (R > 1 && next - tau < margin))
-                    a.flags[0] |= 4;
+        }
+        double bound = 0.0;
+        if (a.guard > 0.0 && a.split_stats) {
+            // The cut must survive the split representation's error in the
+            // tail sums (EigArgs::guard): a model standard deviation at each
+            // side, sqrt(4 delta^2 t + 2 K delta^4 (J - r)) for the tail t
+            // beyond rank r.  R = J discards nothing and is exact.
+            const double d2 = a.split_stats[0];
+            const double dl2 = ldexp(1.0, 2 * ((int)a.split_stats[1] - 16)) / 3.0;
+            auto margin = [&](double t, int r) {
+                return a.guard * sqrt(4.0 * dl2 * t + 2.0 * a.ncols * dl2 * dl2 * (double)(Jv - r)) +
+                       kSplitModelError * d2;
+            };
+            const double next = tail + val(R - 1);
+            bound = R == Jv ? 0.0 : margin(fmax(tail, 0.0), R);
+            if (eps_rule) {
+                const bool below = tau - tail >= bound;
+                const bool above = R == 1 || next - tau >= margin(fmax(next, 0.0), R - 1);
+                if (!(below && above)) a.flags[0] |= 4;
             }
         }
+        if (a.tail_bound) *a.tail_bound = bound;
         int flag = 0;
         if (R > a.max_rank) {
             flag |= 2;
             R = a.max_rank;
         }
         *a.rank_out = R;
-        *a.disc_out = tail;
+        *a.disc_out = fmax(tail, 0.0);
         if (flag) a.flags[0] |= flag;  // single writer: thread 0 of the only workgroup
         misc[0] = R;
         // shifts for inverse iteration: separate (near-)equal eigenvalues
@@ -970,7 +986,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __rest
     EigArgs a = args[blockIdx.x];
     if (conditional) {
         if (!(a.flags[0] & 4)) return;  // uniform over the workgroup
-        a.guard = 0.0;
+        a.guard = 0.0;                  // an FP64 Gram: plain rank rule
+        a.split_stats = nullptr;
     }
     eig_body<JP, PH>(a, region);
     if (conditional) {

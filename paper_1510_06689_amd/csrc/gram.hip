@@ -172,13 +172,47 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
     return acc;
 }
 
+// {sum over p of aux[2 p], max over p of aux[2 p + 1]} -> out[0..1], summed
+// by the first wave of a workgroup in a fixed order (lane-strided partial
+// sums, then lane by lane).
+__device__ __forceinline__ void reduce_split_stats(const double* __restrict__ aux, int P,
+                                                   double* __restrict__ out, double* part) {
+    const int lane = threadIdx.x;
+    if (lane < 64) {
+        double d = 0.0, e = -125.0;
+        for (int q = lane; q < P; q += 64) {
+            d += aux[2 * q];
+            e = fmax(e, aux[2 * q + 1]);
+        }
+        part[lane] = d;
+        part[64 + lane] = e;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double d = 0.0, e = -125.0;
+        for (int k = 0; k < 64; ++k) {
+            d += part[k];
+            e = fmax(e, part[64 + k]);
+        }
+        out[0] = d;
+        out[1] = e;
+    }
+}
+
 // S[r + J c] for the upper block pairs.  Each workgroup reduces 64 outputs;
 // its 4 wave-sized groups sum the partials p = g, g + 4, ... and the four
-// group sums are added in a fixed order.
+// group sums are added in a fixed order.  With aux, one more workgroup
+// reduces the split statistics into stats.
 __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ partial, int P,
                                                    int npairs, int nb, int J,
-                                                   double* __restrict__ s) {
+                                                   double* __restrict__ s,
+                                                   const double* __restrict__ aux,
+                                                   double* __restrict__ stats) {
     __shared__ double part[4][64];
+    if (aux && blockIdx.x == gridDim.x - 1) {  // uniform over the workgroup
+        reduce_split_stats(aux, P, stats, &part[0][0]);
+        return;
+    }
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int idx = blockIdx.x * 64 + o;
     const int n = npairs * 256;
@@ -455,10 +489,11 @@ static int dispatch_partial(const T* y, const ModeView& v, const GramPlan& pl, d
 }
 
 int launch_gram_reduce(const double* partial, const GramPlan& pl, int J, double* s,
-                       hipStream_t st) {
+                       const double* aux, double* stats, hipStream_t st) {
     int n = pl.npairs * 256;
-    hipLaunchKernelGGL(gram_reduce, dim3((n + 63) / 64), dim3(256), 0, st, partial, pl.P,
-                       pl.npairs, pl.nb, J, s);
+    const int nblk = (n + 63) / 64 + (aux ? 1 : 0);
+    hipLaunchKernelGGL(gram_reduce, dim3(nblk), dim3(256), 0, st, partial, pl.P, pl.npairs,
+                       pl.nb, J, s, aux, stats);
     TK_HIP(hipGetLastError());
     return TK_OK;
 }
@@ -479,7 +514,8 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int n = tk.npairs * 256;
     const int P = *tk.nparts;  // slots the Gram launch wrote (<= tk.P)
-    if (w < tk.nwg - 1 || tk.nu == nullptr) {
+    const bool extra = tk.nu != nullptr || (tk.aux != nullptr && !conditional);
+    if (w < tk.nwg - 1 || !extra) {
         const int idx = w * 64 + o;
         const double acc = idx < n ? sum_partials(tk.partial, P, n, idx, g) : 0.0;
         part[g][o] = acc;
@@ -495,8 +531,14 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
         tk.s[r + (int64_t)tk.J * c] = tot;
         tk.s[c + (int64_t)tk.J * r] = tot;
     } else {
-        // the problem's last workgroup: trace of its diagonal from the partials
+        // the problem's last workgroup: split statistics of the unconditional
+        // (split) pass, and the trace of its diagonal from the partials
         // (diagonal 16-blocks p = bi nb - bi (bi - 1) / 2), fixed order
+        if (tk.aux != nullptr && !conditional) {
+            reduce_split_stats(tk.aux, P, tk.stats, &part[0][0]);
+            __syncthreads();
+        }
+        if (tk.nu == nullptr) return;
         if (threadIdx.x < 64) {
             double acc = 0.0;
             for (int i = o; i < tk.J; i += 64) {
@@ -588,7 +630,8 @@ int launch_gram_f64_batched(const BatchGramTask* tasks_dev, int ntasks, int tota
 }
 
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
-                double* sumsq, void* ws, size_t ws_bytes, hipStream_t st) {
+                double* sumsq, void* ws, size_t ws_bytes, hipStream_t st,
+                double* split_stats) {
     GramPlan pl = plan_gram(v, precision, (int)dtype_size(dtype));
     if (ws_bytes < pl.partial_bytes)
         return fail(TK_ERR_WORKSPACE, "gram workspace %zu < %zu", ws_bytes, pl.partial_bytes);
@@ -607,7 +650,9 @@ int launch_gram(const void* y, int dtype, const ModeView& v, int precision, doub
     } else {
         TK_TRY(dispatch_partial((const float*)y, v, pl, partial, st));
     }
-    TK_TRY(launch_gram_reduce(partial, pl, v.J, s, st));
+    const bool split = precision == TK_GRAM_SPLIT_BF16;
+    const double* aux = split && split_stats ? partial + (size_t)pl.P * pl.npairs * 256 : nullptr;
+    TK_TRY(launch_gram_reduce(partial, pl, v.J, s, aux, split_stats, st));
     if (sumsq) {
         hipLaunchKernelGGL(gram_trace, dim3(1), dim3(64), 0, st, s, v.J, sumsq);
         TK_HIP(hipGetLastError());

@@ -5,21 +5,25 @@
 //
 // Split-bf16 Gram.  The rank rule compares tail sums of eigenvalues with
 // eps^2 ||X||^2 / N, so the Gram's error in the trailing eigenvalues must
-// stay far below that threshold.  Two error sources would not: rounding the
-// running hi*hi sums in FP32, and dropping lo*lo, which off the diagonal is
-// a sum of uncorrelated rounding residues that does not average out of the
-// trailing eigenvalues.  Hence, per tile of KT columns and per row i with
-// max |x| < 2^E_i:
-//     hi = round(x 2^(7 - E_i))           an integer in [-128, 128], exact in bf16
-//     lo = bf16(x 2^(7 - E_i) - hi)       the scaled residual, |lo| <= 1/2
-// and a 32x32 block of S = Y_(n) Y_(n)^T is
-//     2^(E_i + E_j - 14) (H_i H_j^T + [H_i L_j^T + L_i H_j^T + L_i L_j^T])
-// on v_mfma_f32_32x32x16_bf16.  H H^T sums at most 128 products of
-// magnitude <= 2^14 per tile, so its FP32 accumulator is exact; the bracket
-// is at most 2^-7 of it and keeps its own FP32 accumulator.  Both are scaled
-// and added into FP64 registers after every tile.  What remains is the
-// bf16 rounding of lo (2^-17 of the row maximum), an error tied to each
-// element that enters the trailing eigenvalues only at second order.
+// stay far below that threshold.  Rounding inside the products would not
+// (dropping lo*lo, or rounding FP32 partial sums, leaves errors that do not
+// average out of the trailing eigenvalues).  Hence every product and sum on
+// the matrix cores is exact: per tile of KT columns and per row i with
+// max |x| < 2^E_i, s = x 2^(7 - E_i) is rounded to the grid 2^-8 (16-bit
+// fixed point) and split into two 8-bit halves
+//     hi = round(s)                        an integer in [-128, 128]
+//     lo = round(256 (s - hi)) / 256       256 lo an integer in [-128, 128]
+// both exact in bf16, and a 32x32 block of S = Y_(n) Y_(n)^T is
+//     2^(E_i + E_j - 14) (H_i H_j^T + [H_i L_j^T + L_i H_j^T] + L_i L_j^T)
+// on v_mfma_f32_32x32x16_bf16, the three terms in three FP32 accumulators:
+// over at most 128 columns each sum is an integer multiple of its quantum
+// (1, 2^-8, 2^-16) below 2^22 of it, so exact.  They are scaled and added
+// into FP64 registers after every tile.  What remains is the quantization
+// error d = s - hi - lo, |d| <= 2^-9, of every element: the split Gram is
+// exactly Y~ Y~^T with Y~ = Y - D.  Quantization noise independent of the
+// data adds its energy to the diagonal, so sum_k d_ik^2 (formed exactly
+// per element) is subtracted from S_ii; the rest of D's contribution has
+// mean zero (see EigArgs::guard for the model and the bound it gives).
 // Partials use the FP64 Gram's 16x16 pair layout and its fixed-order
 // reduction.
 //
@@ -83,6 +87,12 @@ struct SplitTile {
     int i0, cg0;
     bool owner;      // kUnit: this wave holds rows
     int coff[8];     // strided: offsets of the thread's 8 columns inside a tile
+    // Representation error of the split: per row of the thread, the sum of
+    // d^2 over its elements, d = x - 2^(E-7) (hi + lo) exactly, and the
+    // largest row exponent E it used.
+    static constexpr int NROW = MODE == kUnit ? 1 : NGRP;
+    double rd[NROW];
+    int emax;
 
     __device__ static __forceinline__ int64_t col_offset(int kk, int64_t L, int J) {
         const int64_t bb = kk / L;
@@ -90,6 +100,9 @@ struct SplitTile {
     }
 
     __device__ __forceinline__ void setup(const TileMap& tm, int tid) {
+#pragma unroll
+        for (int m = 0; m < NROW; ++m) rd[m] = 0.0;
+        emax = -125;
         if (MODE == kUnit) {
             const int w = tid >> 6, l = tid & 63;
             owner = w * RW < JB;
@@ -183,31 +196,81 @@ struct SplitTile {
     }
 
     // Split and store the tile; the row exponents go next to the planes.
+    // The residual x 2^(7-E) - hi - lo of every element is formed exactly in
+    // FP32 (the bf16 rounding error of lo) and its square summed, rescaled
+    // by 2^(2 (E-7)) per row.
     __device__ __forceinline__ void store(__bf16* hi, __bf16* lo, int* ex) {
         unsigned mb = 0;
         if (MODE == kUnit) mb = row_max_bits(0);  // every group of the thread is one row
+        float rs = 0.f;                            // kUnit: the row's scaled sum of d^2
+        int sh = 0;
 #pragma unroll
         for (int m = 0; m < NGRP; ++m) {
-            if (MODE != kUnit) mb = row_max_bits(m);
-            // max |x| < 2^E; zero rows get the smallest normal exponent
-            const int E = (int)(mb >> 23) - 126;
-            const int sh = 7 - (E < -125 ? -125 : E);
+            if (MODE != kUnit || m == 0) {
+                if (MODE != kUnit) mb = row_max_bits(m);
+                // max |x| < 2^E; zero rows get the smallest normal exponent
+                const int E = (int)(mb >> 23) - 126;
+                sh = 7 - (E < -125 ? -125 : E);
+            }
             bf8_t h, l;
+            float gs = 0.f;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
+                // s = x 2^(7-E) rounded to the grid 2^-8: h + l, h and 256 l
+                // integers in [-128, 128] (exact in bf16); d = s - h - l exactly
                 const float sx = __builtin_ldexpf(v[m][e], sh);
-                const float d = __builtin_rintf(sx);
-                h[e] = (__bf16)d;
-                l[e] = (__bf16)(sx - d);
+                const float hv = __builtin_rintf(sx);
+                const float r = sx - hv;
+                const float lv = __builtin_rintf(r * 256.f) * 0.00390625f;
+                h[e] = (__bf16)hv;
+                l[e] = (__bf16)lv;
+                const float dd = r - lv;
+                gs = __builtin_fmaf(dd, dd, gs);
             }
             const int r = row_of(m);
-            if (MODE != kUnit || owner) {
+            const bool mine = MODE != kUnit || owner;
+            if (mine) {
                 const int off = r * PK + 8 * cg_of(m);
                 *(bf8_t*)(hi + off) = h;
                 *(bf8_t*)(lo + off) = l;
                 if (cg_of(m) == 0) ex[r] = 7 - sh;
             }
+            if (MODE == kUnit) {
+                rs += gs;
+            } else if (r < JB) {
+                rd[m] += __builtin_ldexp((double)gs, -2 * sh);
+                emax = max(emax, 7 - sh);
+            }
         }
+        if (MODE == kUnit && owner) {
+            rd[0] += __builtin_ldexp((double)rs, -2 * sh);
+            emax = max(emax, 7 - sh);
+        }
+    }
+
+    // Per-row sums of d^2 over the workgroup into rowd[0..JB) (each row's
+    // holders form a fixed xor-butterfly; rows nobody holds stay as set).
+    __device__ __forceinline__ void row_sums(double* rowd, int lane) const {
+        if (MODE == kUnit) {
+            double v = rd[0];
+#pragma unroll
+            for (int d = RW; d < 64; d *= 2) v += __shfl_xor(v, d);
+            if (owner && lane < RW) rowd[i0] = v;
+        } else {
+#pragma unroll
+            for (int m = 0; m < NROW; ++m) {
+                double v = rd[m];
+#pragma unroll
+                for (int d = 1; d < NCG; d *= 2) v += __shfl_xor(v, d);
+                if (cg0 == 0) rowd[row_of(m)] = v;
+            }
+        }
+    }
+    __device__ __forceinline__ double total() const {
+        double t = 0.0;
+#pragma unroll
+        for (int m = 0; m < NROW; ++m) t += rd[m];
+        return t;
     }
 };
 
@@ -236,11 +299,41 @@ constexpr size_t mx_buf_bytes() {
 // The body processes tiles [t0, t1) of pair group `group` and writes its
 // partial (npairs16 x 256 doubles) to `out`; the single-tensor kernel and the
 // batched kernel differ only in how they find those.
+// Sum of d over the workgroup (fixed order: lanes by xor butterfly, then
+// waves by index) and max of e; thread 0 writes {sum, max} to aux.
+__device__ __forceinline__ void split_stats_out(double d, int e, double* aux, double* lds) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        d += __shfl_xor(d, o);
+        e = max(e, __shfl_xor(e, o));
+    }
+    int* le = (int*)(lds + kMxWaves);
+    if (lane == 0) {
+        lds[wave] = d;
+        le[wave] = e;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        int m = -125;
+        const int nw = (int)(blockDim.x >> 6);  // at most kMxWaves
+        for (int w = 0; w < nw; ++w) {
+            t += lds[w];
+            m = max(m, le[w]);
+        }
+        aux[0] = t;
+        aux[1] = (double)m;
+    }
+}
+
+// aux (may be NULL): receives {sum of d^2, largest row exponent} of the split
+// representation of the tiles this workgroup processed.
 template <int JB, int KT, int NPW, int MODE>
 __device__ __forceinline__ void gram_bf16s_body(
     const float* __restrict__ y, const TileMap& tm, int npairs32, int pairs_per_group,
     int npairs16, int group, int64_t t0, int64_t t1, double* __restrict__ out,
-    double* lds_raw) {
+    double* aux, double* lds_raw) {
     using Ld = SplitTile<JB, KT, MODE>;
     constexpr int PK = Ld::PK;
     constexpr int PLANE = JB * PK;
@@ -264,7 +357,7 @@ __device__ __forceinline__ void gram_bf16s_body(
         boff[q] = (32 * bj[q] + r32) * PK + 8 * kh;
     }
 
-    f16_t acch[NPW], accr[NPW];
+    f16_t acch[NPW], accm[NPW], accl[NPW];
     double accd[NPW][16];
 #pragma unroll
     for (int q = 0; q < NPW; ++q) {
@@ -296,7 +389,8 @@ __device__ __forceinline__ void gram_bf16s_body(
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 acch[q][v] = 0.f;
-                accr[q][v] = 0.f;
+                accm[q][v] = 0.f;
+                accl[q][v] = 0.f;
             }
 #pragma unroll 2
             for (int ks = 0; ks < NKS; ++ks) {
@@ -305,9 +399,9 @@ __device__ __forceinline__ void gram_bf16s_body(
                 const bf8_t bh = *(const bf8_t*)(hb + boff[q] + 16 * ks);
                 const bf8_t bl = *(const bf8_t*)(lb + boff[q] + 16 * ks);
                 acch[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acch[q], 0, 0, 0);
-                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, accr[q], 0, 0, 0);
-                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, accr[q], 0, 0, 0);
-                accr[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, accr[q], 0, 0, 0);
+                accm[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, accm[q], 0, 0, 0);
+                accm[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, accm[q], 0, 0, 0);
+                accl[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, accl[q], 0, 0, 0);
             }
             // v_mfma_f32_32x32x16: row (v / 4) * 8 + (lane / 32) * 4 + v % 4, column lane % 32
             const int ej = ex[32 * bj[q] + r32] - 14;
@@ -317,7 +411,7 @@ __device__ __forceinline__ void gram_bf16s_body(
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int v = 4 * g + c;
-                    const double sv = (double)acch[q][v] + (double)accr[q][v];
+                    const double sv = (double)acch[q][v] + ((double)accm[q][v] + (double)accl[q][v]);
                     accd[q][v] += __builtin_ldexp(sv, ei[c] + ej);
                 }
             }
@@ -329,6 +423,17 @@ __device__ __forceinline__ void gram_bf16s_body(
         __syncthreads();
     }
 
+    // With D = Y - Y~ (Y~ the split representation) the products form
+    // Y~ Y~^T = Y Y^T - Y D^T - D Y^T + D D^T: rounding errors independent of
+    // the data add their energy, diag(D D^T), to the diagonal, which would
+    // raise every tail sum by about ||D||_F^2 (J - R) / J.  That diagonal,
+    // sum_k d_ik^2, is known exactly per row and is subtracted here; what
+    // remains (Y D^T + D Y^T and the off-diagonal of D D^T) has mean 0.
+    double* rowd = lds_raw + 64;  // past split_stats_out's slots
+    for (int i = tid; i < JB; i += kMxThreads) rowd[i] = 0.0;
+    __syncthreads();
+    ld.row_sums(rowd, lane);
+    __syncthreads();
     constexpr int NB16 = 2 * NB;
 #pragma unroll
     for (int q = 0; q < NPW; ++q) {
@@ -340,12 +445,15 @@ __device__ __forceinline__ void gram_bf16s_body(
             const int BI = gi >> 4, BJ = gj >> 4;
             if (BI > BJ) continue;  // lower half of a diagonal 32-block
             const int p16 = BI * NB16 - BI * (BI - 1) / 2 + (BJ - BI);
-            out[(int64_t)p16 * 256 + (gi & 15) * 16 + (gj & 15)] = accd[q][v];
+            out[(int64_t)p16 * 256 + (gi & 15) * 16 + (gj & 15)] =
+                gi == gj ? accd[q][v] - rowd[gi] : accd[q][v];
         }
     }
+    if (aux) split_stats_out(ld.total(), ld.emax, aux, lds_raw);  // uniform branch
 }
 
-// P tile ranges x G pair groups, one workgroup each (xcd_range_group).
+// P tile ranges x G pair groups, one workgroup each (xcd_range_group).  The
+// P x 2 split statistics follow the P partials; pair group 0 writes them.
 template <int JB, int KT, int NPW, int MODE>
 __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
     const float* __restrict__ y, TileMap tm, int npairs32, int pairs_per_group, int npairs16,
@@ -355,8 +463,9 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
     xcd_range_group(blockIdx.x, G, p, g);
     const int64_t t0 = tm.ntiles * (int64_t)p / P;
     const int64_t t1 = tm.ntiles * (int64_t)(p + 1) / P;
+    double* aux = g == 0 ? partial + (int64_t)P * npairs16 * 256 + 2 * p : nullptr;
     gram_bf16s_body<JB, KT, NPW, MODE>(y, tm, npairs32, pairs_per_group, npairs16, g, t0, t1,
-                                      partial + (int64_t)p * npairs16 * 256, lds_raw);
+                                      partial + (int64_t)p * npairs16 * 256, aux, lds_raw);
 }
 
 // Static schedule per padded extent: tile width, pairs per wave, pair groups
@@ -396,8 +505,9 @@ static GramPlan mx_plan(const ModeView& v) {
     pl.npairs = pl.nb * (pl.nb + 1) / 2;
     const int64_t want = xcd_round_want((int64_t)gs.per_cu * device_cu_count() / pl.G, pl.G);
     pl.P = xcd_ranges(tm.ntiles, want, pl.G);
-    pl.partial_bytes = (size_t)pl.P * pl.npairs * 256 * sizeof(double);
-    pl.partial_bound = (size_t)want * pl.npairs * 256 * sizeof(double);
+    // partials, then 2 doubles of split statistics per tile range
+    pl.partial_bytes = (size_t)pl.P * (pl.npairs * 256 + 2) * sizeof(double);
+    pl.partial_bound = (size_t)want * (pl.npairs * 256 + 2) * sizeof(double);
     return pl;
 }
 
@@ -456,12 +566,16 @@ __global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
     const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / active;
     constexpr int nb32 = JB / 32, np32 = nb32 * (nb32 + 1) / 2, np16 = 2 * nb32 * (2 * nb32 + 1) / 2;
     double* out = tk.partial + (int64_t)w * np16 * 256;
+    double* aux = tk.aux + 2 * w;
     if (mv.L == 1)
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kUnit>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kUnit>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
+                                                  aux, lds_raw);
     else if (mv.L % 8 == 0 && ((uintptr_t)tk.y & 15) == 0)
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kContig>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kContig>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
+                                                    aux, lds_raw);
     else
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kStrided>(tk.y, tm, np32, np32, np16, 0, t0, t1, out, lds_raw);
+        gram_bf16s_body<JB, gs.KT, gs.NPW, kStrided>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
+                                                     aux, lds_raw);
 }
 
 int mx_gram_kt(int jb) {

@@ -163,8 +163,11 @@ GramPlan plan_gram(const ModeView& v, int precision, int elem_bytes);
 GramPlan plan_gram_mixed(const ModeView& v);
 int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, double* partial,
                       hipStream_t st);
+// split_stats (may be NULL; split-bf16 Grams only): receives {sum of d^2,
+// largest row exponent} of the split representation (see EigArgs).
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
-                double* sumsq, void* ws, size_t ws_bytes, hipStream_t st);
+                double* sumsq, void* ws, size_t ws_bytes, hipStream_t st,
+                double* split_stats = nullptr);
 
 int launch_ttm(const void* y, int dtype, const ModeView& v, const double* m, int64_t K,
                int64_t ldm, int transpose, int precision, void* z, hipStream_t st);
@@ -187,8 +190,28 @@ struct EigArgs {
     int* flags;            // device status flags (bit 0: no convergence, bit 1: capacity,
                            // bit 2: rank within the guard margin)
     double* scratch;       // eig_scratch_doubles(J)
-    double guard = 0.0;    // > 0: flag a rank decision closer to the threshold than
-                           // guard * trace * R (J - R) / J^2 (mixed-precision Grams)
+    // Guard of a rank found from a split-bf16 Gram.  With Y the unfolding
+    // (K columns), Y~ its split representation and D = Y - Y~, the Gram
+    // formed is Y~ Y~^T - diag(D D^T) (the diagonal of D D^T is subtracted
+    // exactly, per row), so the computed tail sum t~_R and the exact t_R
+    // differ by tr((I-Q) F) with F = offdiag(D D^T) - Y D^T - D Y^T, Q the
+    // projector onto the kept space.  The products are exact (the split's
+    // halves are 8-bit integers), so D is the whole error; modelling its
+    // entries d as quantization noise independent of the data and of each
+    // other, mean 0, |d| <= 2^(E_max - 16) (uniform: variance at most
+    // delta^2 = 4^(E_max - 16) / 3), tr((I-Q) F) has mean 0 and variance at
+    // most 4 delta^2 t + 2 K delta^4 (J - R).  The subtracted diagonal rests
+    // on the same model (independent noise adds exactly its energy), so it is
+    // trusted only to kSplitModelError of its size, ||D||_F^2.  The bound is
+    // `guard` standard deviations of the first part plus
+    // kSplitModelError ||D||_F^2 (at t~_R); under the eps rule the rank is
+    // certified when tau - t~_R and t~_{R-1} - tau both exceed that bound at
+    // their own t and rank; otherwise flag bit 2.
+    double guard = 0.0;
+    const double* split_stats = nullptr;  // device {sum of d^2, E_max} of the Gram
+    double ncols = 0.0;                   // K, the unfolding's columns (an upper bound)
+    double* tail_bound = nullptr;         // device out (may be NULL): the bound on
+                                          // |t_R - t~_R|; 0 without the guard
     int aug = 0;           // 1: s is [[0, R^T], [R, 0]] (J = 2 J_R): its leading J_R
                            // eigenvalues are sigma_i(R); lambda (J_R values) and the
                            // rank rule use sigma_i^2, u receives 2 J_R x R vectors
@@ -211,15 +234,30 @@ int launch_jw(const double* r, int J, double* m, hipStream_t st);
 int launch_jw_extract(const double* z, int J, int max_rank, const int64_t* rank, double* u,
                       hipStream_t st);
 
-// Error scale of the split-bf16 Gram in the trailing eigenvalue sums, per
-// unit of trace * R (J - R) / J^2: signal/tail coupling through the bf16
-// residuals is about 2^-30 there; the guard keeps a factor 8 above it.
-constexpr double kSplitGramGuard = 8.0 / 1073741824.0;
+// Standard deviations of the model's error terms the split-Gram guard
+// allows for (EigArgs::guard), and the share of ||D||_F^2 it allows for the
+// subtracted diagonal (an emulation of this split on combustion-like data
+// found the corrected tail sums off by up to about 3% of ||D||_F^2 when
+// ||D||_F^2 is a hundred times the threshold, and by 0.04% near it).
+constexpr double kSplitGramGuard = 6.0;
+constexpr double kSplitModelError = 0.125;
 
 // The split-bf16 TTM leaves a relative error of about 2^-17 in every output,
 // which adds about 2^-34 ||X||^2 to later modes' tail sums; below
 // eps^2 / N = 8 * 2^-34 the threshold would feel it, so the TTMs run in FP64.
 constexpr double kSplitTtmFloor = 8.0 / 17179869184.0;
+// The plain bf16 TTM (both operands rounded to bf16) leaves about 2^-8, i.e.
+// about 2^-16 ||X||^2 in later tail sums: under the eps rule it keeps the
+// same factor 8 only for eps^2 / N >= 8 * 2^-16.
+constexpr double kBf16TtmFloor = 8.0 / 65536.0;
+// TTM arithmetic under the eps rule: a requested precision whose error would
+// reach the rank threshold is raised to the next more accurate one.
+inline int ttm_precision_for_eps(int requested, double eps2_over_n) {
+    int p = requested;
+    if (p == TK_TTM_BF16 && eps2_over_n < kBf16TtmFloor) p = TK_TTM_BF16X3;
+    if (p == TK_TTM_BF16X3 && eps2_over_n < kSplitTtmFloor) p = TK_TTM_FP64;
+    return p;
+}
 // Mixed path: modes with J <= 32 and at most this many unfolding elements
 // use the FP64 Gram (2^26: 256 MB of FP32), and so does any mode the FP64
 // narrow-mode kernel takes.
@@ -317,6 +355,7 @@ struct BatchGramTask {
     BatchView v;
     const float* y;
     double* partial;     // nwg partial slots
+    double* aux;         // nwg x 2 split statistics (split-bf16 Gram)
     const int* status;   // the problem's status word (bit 4: rank not certified)
     int* nparts;         // partial slots written by the last Gram launch
     int tpw;             // split-Gram tiles per workgroup
@@ -331,6 +370,8 @@ struct BatchReduceTask {
     const double* partial;
     double* s;
     double* nu;  // trace target or nullptr
+    const double* aux;  // split statistics per partial slot, or nullptr
+    double* stats;      // {sum of d^2, E_max} over the slots written (with aux)
     int P, npairs, nb, J;  // P: partial slots reserved (the sum runs over *nparts)
     int wg_begin, nwg;
     const int* status;

@@ -66,7 +66,8 @@ class Tucker(ctypes.Structure):
                 ("factors_dev", ctypes.c_void_p * MAX_NDIM), ("eigvals_dev", ctypes.c_void_p),
                 ("ranks", ctypes.c_int64 * MAX_NDIM), ("discarded", ctypes.c_double * MAX_NDIM),
                 ("norm2", ctypes.c_double), ("fp64_modes", ctypes.c_uint32),
-                ("ttm_precision_used", ctypes.c_int32)]
+                ("ttm_precision_used", ctypes.c_int32),
+                ("tail_error_bound", ctypes.c_double * MAX_NDIM)]
 
 
 class BatchOutputs(ctypes.Structure):
@@ -74,7 +75,8 @@ class BatchOutputs(ctypes.Structure):
                 ("core_capacity", ctypes.POINTER(ctypes.c_int64)),
                 ("factors_dev", ctypes.POINTER(ctypes.c_void_p)),
                 ("ranks_dev", ctypes.c_void_p), ("discarded_dev", ctypes.c_void_p),
-                ("norm2_dev", ctypes.c_void_p), ("status_dev", ctypes.c_void_p)]
+                ("norm2_dev", ctypes.c_void_p), ("status_dev", ctypes.c_void_p),
+                ("tail_bound_dev", ctypes.c_void_p)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -279,6 +281,7 @@ class TuckerTensor:
     norm2: float                  # ||X||^2
     fp64_modes: tuple = ()        # modes whose split-bf16 Gram was redone in FP64
     ttm_precision: str = "fp64"   # arithmetic the TTMs actually ran in
+    tail_error_bound: tuple = ()  # per mode: bound on |discarded - exact tail sum|
 
     @property
     def full_dims(self):
@@ -385,7 +388,7 @@ class Compressor:
             r = self.result()
             return TuckerTensor(_fortran_copy(r.core), [_fortran_copy(f) for f in r.factors],
                                 r.ranks, [e.clone() for e in r.eigvals], r.discarded, r.norm2,
-                                r.fp64_modes, r.ttm_precision)
+                                r.fp64_modes, r.ttm_precision, r.tail_error_bound)
         n = len(self.dims)
         ranks = tuple(int(self.out.ranks[k]) for k in range(n))
         core = self.core_buf[:math.prod(ranks)].view(tuple(reversed(ranks))).permute(
@@ -400,7 +403,8 @@ class Compressor:
                             tuple(float(self.out.discarded[k]) for k in range(n)),
                             float(self.out.norm2),
                             tuple(k for k in range(n) if self.out.fp64_modes >> k & 1),
-                            _TTM_NAMES[int(self.out.ttm_precision_used)])
+                            _TTM_NAMES[int(self.out.ttm_precision_used)],
+                            tuple(float(self.out.tail_error_bound[k]) for k in range(n)))
 
 
 def sthosvd(x: torch.Tensor, eps: float, order=None, ranks=None, max_ranks=None,
@@ -546,6 +550,7 @@ class BatchCompressor:
         self.disc_dev = torch.zeros(b * n, dtype=torch.float64, device=dev)
         self.norm2_dev = torch.zeros(b, dtype=torch.float64, device=dev)
         self.status_dev = torch.zeros(2 * b, dtype=torch.int32, device=dev)
+        self.bound_dev = torch.zeros(b * n, dtype=torch.float64, device=dev)
         self._cores = (_vp * b)(*[t.data_ptr() for t in self.core_bufs])
         self._caps = (_i64 * b)(*[t.numel() for t in self.core_bufs])
         facs = (_vp * (b * MAX_NDIM))()
@@ -555,7 +560,7 @@ class BatchCompressor:
         self._facs = facs
         self.outs = BatchOutputs(self._cores, self._caps, self._facs, self.ranks_dev.data_ptr(),
                                  self.disc_dev.data_ptr(), self.norm2_dev.data_ptr(),
-                                 self.status_dev.data_ptr())
+                                 self.status_dev.data_ptr(), self.bound_dev.data_ptr())
         self.ws = _workspace(need, dev)
         xp = (_vp * b)(*[x.data_ptr() for x in self.xs])
         self._xp = xp
@@ -596,6 +601,7 @@ class BatchCompressor:
         disc = self.disc_dev.view(-1, n).cpu().tolist()
         norm2 = self.norm2_dev.cpu().tolist()
         status = self.status_dev.view(-1, 2).cpu().tolist()
+        bounds = self.bound_dev.view(-1, n).cpu().tolist()
         out = []
         for i, d in enumerate(self.dims):
             r = tuple(int(v) for v in ranks[i])
@@ -604,7 +610,8 @@ class BatchCompressor:
             facs = [self.factor_bufs[i][k][:d[k] * r[k]].view(r[k], d[k]).t() for k in range(n)]
             out.append(TuckerTensor(core, facs, r, [], tuple(disc[i]), float(norm2[i]),
                                     tuple(k for k in range(n) if status[i][1] >> k & 1),
-                                    _TTM_NAMES[int(self.opt.ttm_precision)]))
+                                    _TTM_NAMES[int(self.opt.ttm_precision)],
+                                    tuple(bounds[i])))
         return out
 
     def __del__(self):

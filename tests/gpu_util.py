@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests: moving Fortran-strided tensors between the
 host and the device, and rounding-error bounds used as tolerances."""
+import math
 import sys
 
 import numpy as np
@@ -53,10 +54,71 @@ def mode1_rows(x, i, j):
 
 def split_gram_bound(sub):
     """Elementwise bound of the split-bf16 Gram (mode 1) of a row slice:
-    2^-16 (m_i |x_j|_1 + m_j |x_i|_1) + 2^-24 K m_i m_j."""
+    2^-15 (m_i |x_j|_1 + m_j |x_i|_1) + 2^-30 K m_i m_j (16-bit fixed-point
+    representation to 2^-15 m_i, exact products, the diagonal of D D^T
+    subtracted)."""
     import oracle
     m = oracle.unfold(sub, 0)
     rmax = np.abs(m).max(axis=1)
     l1 = np.abs(m).sum(axis=1)
     k = m.shape[1]
-    return 2.0**-16 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-24 * k * np.outer(rmax, rmax)
+    return 2.0**-15 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-30 * k * np.outer(rmax, rmax)
+
+
+# Relative error per element of one TTM's output, by arithmetic (taken as a
+# bound on ||dZ|| / ||Y|| for the product): split-bf16 keeps 16 bits of both
+# operands (about 2^-17 per product; 2^-16 allows for the sum), plain bf16 8
+# bits; FP64 arithmetic leaves only the output's storage rounding (below).
+TTM_REL = {"bf16x3": 2.0**-16, "bf16": 2.0**-7, "fp64": 0.0}
+
+
+def carried_errors(res, ref, dims, order, ttm, storage_u, e0=0.0):
+    """Per mode n (processing order), how far the GPU's discarded sum may lie
+    from the oracle's when both pick the same ranks:
+
+      tol_n = b_n + 2 sqrt(t_n) e_n + e_n^2 + 16 (sqrt(K_n) + J_n) u nu
+
+    b_n   the library's own bound for a split-bf16 Gram of the GPU's Y_n
+          (tk_tucker.tail_error_bound; 0 for FP64 Grams),
+    e_n   the norm of the difference between the GPU's Y_n and the oracle's:
+          the errors of the earlier TTMs, e_n^2 = nu sum_{m before n} c_m^2
+          (|sqrt(t(A)) - sqrt(t(B))| <= ||A - B||_F for the tail energy t of a
+          fixed-rank truncation, so |dt| <= 2 sqrt(t) e + e^2), c_m from
+          TTM_REL plus the storage rounding storage_u of each product,
+    the last term FP64 rounding of either Gram (K_n columns, J_n rows).
+    e0 (relative to ||X||) is a difference already in the inputs (another
+    storage of the same tensor).  Returns ({mode: tol_n}, e_N^2) with e_N the
+    same for the core."""
+    nu = ref.norm2
+    c2 = TTM_REL[ttm] ** 2 + storage_u ** 2
+    cur = list(dims)
+    e2 = e0 * e0 * nu
+    tol = {}
+    for n in order:
+        k = math.prod(cur) // cur[n]
+        t = max(ref.discarded[n], 0.0)
+        tol[n] = (res.tail_error_bound[n] + 2 * math.sqrt(t * e2) + e2 +
+                  16 * (math.sqrt(k) + cur[n]) * U64 * nu)
+        e2 += c2 * nu
+        cur[n] = res.ranks[n]
+    return tol, e2
+
+
+def check_against_oracle(res, ref, dims, order, ttm, rel, rel_ref, storage_u=U32, e0=0.0):
+    """Same ranks; every mode's discarded sum within carried_errors; and the
+    reconstruction errors (rel of the GPU's X~, stored with unit roundoff
+    storage_u, rel_ref the oracle's) within what those imply: by the ST-HOSVD
+    identity ||X - X~||^2 = sum of discarded, up to the core's carried error
+    e_N and the storage rounding of X~.  Returns sum of tol_n / nu."""
+    assert res.ranks == ref.ranks, (res.ranks, ref.ranks)
+    order = tuple(range(len(dims))) if order is None else tuple(order)
+    tol, eN2 = carried_errors(res, ref, dims, order, ttm, storage_u, e0)
+    for n in order:
+        d = abs(res.discarded[n] - ref.discarded[n])
+        assert d <= tol[n], (n, res.discarded[n], ref.discarded[n], tol[n],
+                             res.tail_error_bound[n])
+    nu = ref.norm2
+    ex2 = eN2 + storage_u ** 2 * nu
+    slack = sum(tol.values()) + 2 * math.sqrt(rel_ref ** 2 * nu * ex2) + ex2
+    assert abs(rel ** 2 - rel_ref ** 2) * nu <= slack, (rel, rel_ref, slack / nu)
+    return sum(tol.values()) / nu

@@ -191,6 +191,35 @@ def test_reconstruct_and_metrics_validation():
     assert lib.tucker_error_metrics(None, FAKE, FAKE, None, None, 0, None) == -1
 
 
+def test_batch_ttm_precision_floor():
+    """Under the eps rule a batch refuses a TTM precision whose output error
+    would reach the rank threshold (it has no output to report a raised
+    precision in): bf16 needs eps^2/N >= 2^-13, split-bf16 eps^2/N >= 2^-31."""
+    lib = tk.library()
+    shapes = (tk.Shape * 2)(shape([8, 8, 8, 4], tk.F32), shape([6, 8, 8, 4], tk.F32))
+
+    def need(eps, ttm, ranks=None):
+        keep = []
+        opt = tk._options(4, eps, None, ranks, None, "split_bf16", ttm, keep)
+        return lib.sthosvd_batch_workspace_bytes(2, shapes, ctypes.byref(opt), None)
+
+    floor_bf16 = (4 * 2.0 ** -13) ** 0.5      # eps with eps^2 / 4 = 2^-13
+    floor_x3 = (4 * 2.0 ** -31) ** 0.5
+    assert need(1.01 * floor_bf16, "bf16") > 0
+    assert need(0.99 * floor_bf16, "bf16") == 0
+    assert "bf16" in last_error() and "TK_TTM_BF16X3" in last_error()
+    assert need(0.99 * floor_bf16, "bf16x3") > 0
+    assert need(1.01 * floor_x3, "bf16x3") > 0
+    assert need(0.99 * floor_x3, "bf16x3") == 0
+    # fixed ranks: no rank decision depends on the TTM, any precision goes
+    assert need(0.0, "bf16", ranks=(2, 2, 2, 2)) > 0
+    h = ctypes.c_void_p()
+    keep = []
+    opt = tk._options(4, 1e-4, None, None, None, "split_bf16", "bf16", keep)
+    assert lib.sthosvd_batch_create(2, shapes, None, ctypes.byref(opt), None, None, None, 0,
+                                    None, ctypes.byref(h)) == -2
+
+
 def test_status_strings():
     lib = tk.library()
     for code in range(0, -8, -1):

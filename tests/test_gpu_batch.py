@@ -11,7 +11,8 @@ import torch
 import oracle
 import synth
 from paper_1510_06689_amd import tucker
-from gpu_util import say, to_dev
+from gpu_util import check_against_oracle, say, to_dev
+from test_gpu_mixed import _first_mode_tie_case
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +48,8 @@ def test_batch_matches_oracle_per_problem():
         xr = oracle.reconstruct(ref.core, ref.factors)
         rel_ref = math.sqrt(float(np.sum((xh - xr) ** 2)) / ref.norm2)
         rel = _relerr(d, r)
-        assert rel <= 1e-4 and abs(rel - rel_ref) <= 1e-4
+        assert rel <= 1e-4
+        check_against_oracle(r, ref, x.shape, None, "bf16x3", rel, rel_ref)
         assert math.isclose(r.norm2, ref.norm2, rel_tol=1e-6)
         for u in r.factors:
             ut = u.cpu().numpy()
@@ -92,38 +94,43 @@ def test_batch_redo_keeps_oracle_ranks_where_uncertain():
 
 
 def test_batch_guard_recomputes_on_device():
-    """Problems of the 64-problem benchmark batch (s^3 x 16, ranks (12,12,12,6),
-    eps = 1e-4): after two truncations the unfoldings' columns decay by rho^r,
-    the split representation error (relative to each row's largest entry)
-    reaches a third of the threshold in the tail sums, and the guard refuses
-    to certify some ranks.  The run must resolve them on the device (no
-    status bit 4 left, recorded per mode), with every rank equal to the
-    oracle's and the error equal to the single-problem path's."""
+    """A batch holding the near-tie case (the first-processed mode, J = 128,
+    cut at t_R = (1 - 1e-4) tau: no split-Gram bound is that small) and three
+    problems of the 64-problem benchmark batch (s^3 x 16, ranks (12,12,12,6),
+    eps = 1e-4): the run must resolve every uncertain rank on the device (no
+    status bit 4 left; the near tie recomputed in FP64 and recorded), with
+    every rank equal to the oracle's, and batch and single-problem results
+    each within their derived bounds of the oracle's discarded sums and
+    error."""
+    xt, xth, eps_t, order_t = _first_mode_tie_case()
     ws = synth.batch_workload()
     pick = [19, 15, 1]                       # s = 56, 28, 57
     xs = [ws[i].make(dtype=torch.float64).float() for i in pick]
-    xd = [to_dev(x) for x in xs]
-    eps = ws[0].eps
-    c = tucker.BatchCompressor(xd, eps)
-    c.run()
-    torch.cuda.synchronize()
-    status = c.status_dev.view(-1, 2).cpu().numpy()
-    assert not (status[:, 0] & 4).any(), status
-    c.finish()
-    res = c.results()
-    assert any(r.fp64_modes for r in res), [r.fp64_modes for r in res]
-    for i, x, d, r in zip(pick, xs, xd, res):
-        ref = oracle.sthosvd(x.double().numpy(), eps)
-        single = tucker.sthosvd(d, eps, gram_precision="split_bf16", ttm_precision="bf16x3")
-        say(f"problem {i} {tuple(x.shape)}: ranks {r.ranks} oracle {ref.ranks} "
-            f"fp64 modes batch {r.fp64_modes} single {single.fp64_modes}")
-        assert r.ranks == ref.ranks == ws[i].ranks
-        rel, rel1 = _relerr(d, r), _relerr(d, single)
-        # the two paths may take a mode's Gram in different precisions (the
-        # single path uses FP64 for narrow small modes): an accepted split
-        # rank keeps the discarded energy within the guard margin,
-        # 8 2^-30 tr R (J - R) / J^2 <= 2^-29 ||X||^2, per mode
-        assert rel <= eps and abs(rel**2 - rel1**2) <= len(x.shape) * 2.0**-29
+    for eps, order, batch in ((eps_t, order_t, [xt]), (ws[0].eps, None, xs)):
+        xd = [to_dev(x) for x in batch]
+        c = tucker.BatchCompressor(xd, eps, order=order)
+        c.run()
+        torch.cuda.synchronize()
+        status = c.status_dev.view(-1, 2).cpu().numpy()
+        assert not (status[:, 0] & 4).any(), status
+        c.finish()
+        res = c.results()
+        if batch is not xs:
+            assert 1 in res[0].fp64_modes, res[0].fp64_modes
+        for x, d, r in zip(batch, xd, res):
+            xh = x.double().numpy()
+            ref = oracle.sthosvd(xh, eps, order=order)
+            single = tucker.sthosvd(d, eps, order=order, gram_precision="split_bf16",
+                                    ttm_precision="bf16x3")
+            say(f"problem {tuple(x.shape)} eps {eps:.3e}: ranks {r.ranks} oracle {ref.ranks} "
+                f"fp64 modes batch {r.fp64_modes} single {single.fp64_modes}")
+            xr = oracle.reconstruct(ref.core, ref.factors)
+            rel_ref = math.sqrt(float(np.sum((xh - xr) ** 2)) / ref.norm2)
+            rel, rel1 = _relerr(d, r), _relerr(d, single)
+            assert rel <= eps and rel1 <= eps
+            check_against_oracle(r, ref, x.shape, order, "bf16x3", rel, rel_ref)
+            check_against_oracle(single, ref, x.shape, order, single.ttm_precision, rel1,
+                                 rel_ref)
 
 
 def test_batch_rejects_unsupported():
