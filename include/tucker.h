@@ -149,6 +149,26 @@ int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, d
                 double* sumsq_dev, void* ws, size_t ws_bytes, void* stream);
 size_t gram_workspace_bytes(const tk_shape* y, int mode, int precision);
 
+/*
+ * gram_mode_n without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and results as gram_mode_n;
+ * the scratch (Gram partials and split statistics) is a static device array
+ * of gram_noalloc_scratch_bytes() bytes (64 MiB), one per device, allocated
+ * with the library's code on that device and held until the process ends.
+ * Shapes whose gram_workspace_bytes exceed it fail with TK_ERR_WORKSPACE;
+ * no shape the library accepts does (the Gram's grid is capped per extent,
+ * so its partials do not grow with the other modes: the largest, J = 337 in
+ * FP64, needs 63.3 MiB).  Argument errors as gram_mode_n, reported before
+ * any device call.  The call allocates nothing
+ * (no hipMalloc, no library allocation).  Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.
+ */
+int gram_mode_n_noalloc(const tk_shape* y, const void* y_dev, int mode, int precision,
+                        double* s_dev, double* sumsq_dev, void* stream);
+size_t gram_noalloc_scratch_bytes(void);
+
 /* -------------------------------------------------------------------- QR */
 
 /* Largest mode extent of the QR path (R is kept in one workgroup's LDS). */

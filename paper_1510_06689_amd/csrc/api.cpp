@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "tk_common.hpp"
@@ -150,6 +151,58 @@ int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, d
     TK_TRY(check_ws(ws, ws_bytes, need, "gram_mode_n"));
     ModeView v = mode_view(y->dims, y->ndim, mode);
     return launch_gram(y_dev, y->dtype, v, precision, s_dev, sumsq_dev, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+// -------------------------------------------------- Gram without allocation
+//
+// The scratch of gram_mode_n_noalloc: a file-scope device array, one copy on
+// each device the library runs on, held until the process ends.  Host code
+// never uses the array's name as an address: each device's copy is looked up
+// once (hipGetSymbolAddress with that device current) and that pointer is what
+// the kernels receive.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int scratch_for_current_device(void** out) {
+    int dev = 0;
+    TK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(TK_ERR_UNSUPPORTED, "gram_mode_n_noalloc: device %d beyond %d", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        TK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TK_OK;
+}
+}  // namespace
+
+size_t gram_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int gram_mode_n_noalloc(const tk_shape* y, const void* y_dev, int mode, int precision,
+                        double* s_dev, double* sumsq_dev, void* stream) {
+    TK_TRY(check_gram_args(y, mode, precision));
+    if (!y_dev || !s_dev)
+        return fail(TK_ERR_INVALID_ARG, "gram_mode_n_noalloc: NULL device pointer");
+    const size_t need = gram_workspace_bytes(y, mode, precision);
+    if (need > kNoAllocScratchBytes)
+        return fail(TK_ERR_WORKSPACE, "gram_mode_n_noalloc: this shape needs %zu bytes of scratch, "
+                    "more than the static %zu", need, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    TK_TRY(scratch_for_current_device(&ws));
+    ModeView v = mode_view(y->dims, y->ndim, mode);
+    // every partial slot the kernels read is written by them first: nothing
+    // in the scratch has to start at zero
+    return launch_gram(y_dev, y->dtype, v, precision, s_dev, sumsq_dev, ws, kNoAllocScratchBytes,
                        (hipStream_t)stream);
 }
 

@@ -34,7 +34,8 @@ STATUS = {0: "TK_OK", -1: "TK_ERR_INVALID_ARG", -2: "TK_ERR_UNSUPPORTED",
           -3: "TK_ERR_WORKSPACE", -4: "TK_ERR_HIP", -5: "TK_ERR_NONFINITE",
           -6: "TK_ERR_EIG_NO_CONVERGENCE", -7: "TK_ERR_CAPACITY"}
 
-EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "qr_r_mode_n", "qr_workspace_bytes",
+EXPORTS = ("gram_mode_n", "gram_workspace_bytes", "gram_mode_n_noalloc",
+           "gram_noalloc_scratch_bytes", "qr_r_mode_n", "qr_workspace_bytes",
            "ttm_mode_n", "sthosvd_compress",
            "sthosvd_workspace_bytes", "tucker_reconstruct", "reconstruct_workspace_bytes",
            "tucker_error_metrics", "error_metrics_workspace_bytes",
@@ -101,6 +102,8 @@ def library() -> ctypes.CDLL:
     sig = {
         "gram_mode_n": (_int, [_pshape, _vp, _int, _int, _vp, _vp, _vp, _sz, _vp]),
         "gram_workspace_bytes": (_sz, [_pshape, _int, _int]),
+        "gram_mode_n_noalloc": (_int, [_pshape, _vp, _int, _int, _vp, _vp, _vp]),
+        "gram_noalloc_scratch_bytes": (_sz, []),
         "qr_r_mode_n": (_int, [_pshape, _vp, _int, _vp, _vp, _vp, _sz, _vp]),
         "qr_workspace_bytes": (_sz, [_pshape, _int]),
         "ttm_mode_n": (_int, [_pshape, _vp, _int, _vp, _i64, _i64, _int, _int, _vp, _vp]),
@@ -230,6 +233,23 @@ def gram(y: torch.Tensor, mode: int, precision: str = "fp64"):
     ws = _workspace(need, y.device)
     _check(lib.gram_mode_n(ctypes.byref(sh), y.data_ptr(), mode, prec, s.data_ptr(),
                            sumsq.data_ptr(), _aligned(ws), need, _stream(y.device)))
+    return s, sumsq
+
+
+def gram_noalloc(y: torch.Tensor, mode: int, precision: str = "fp64", out=None, sumsq=None):
+    """``gram`` through the allocation-free entry point: the library's static
+    per-device scratch instead of a workspace.  ``out`` (J x J FP64) and
+    ``sumsq`` (FP64 scalar) may be given, so that nothing is allocated here
+    either; ``sumsq`` is then only written when given."""
+    _require_device(y)
+    j = y.shape[mode]
+    s = torch.empty((j, j), dtype=torch.float64, device=y.device) if out is None else out
+    if out is None and sumsq is None:
+        sumsq = torch.empty((), dtype=torch.float64, device=y.device)
+    _check(library().gram_mode_n_noalloc(ctypes.byref(shape_of(y)), y.data_ptr(), mode,
+                                         GRAM_PRECISIONS[precision], s.data_ptr(),
+                                         None if sumsq is None else sumsq.data_ptr(),
+                                         _stream(y.device)))
     return s, sumsq
 
 
