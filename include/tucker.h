@@ -74,14 +74,17 @@ typedef enum tk_gram_precision {
     /* FP64 products and FP64 accumulation on FP64 matrix cores (FP32 input is
      * widened exactly). */
     TK_GRAM_FP64 = 0,
-    /* FP32 input only.  Per column tile and row i with max |x| < 2^E_i, each
-     * value's s = x 2^(7-E_i) is rounded to the grid 2^-8 (16-bit fixed
-     * point) and split into hi = round(s) and lo = round(256 (s - hi)) / 256,
-     * both 8-bit integers up to scale and exact in bf16; the four products
-     * hh, hl, lh, ll run on bf16 matrix cores into three FP32 accumulators
-     * (hh; hl + lh; ll) whose sums over a tile are exact, scaled by
-     * 2^(E_i+E_j-14) and added into FP64 after every tile.  Each element is
-     * represented to 2^-16 of 2^E_i.  The quantization error d of every
+    /* FP32 input only (the name stays for compatibility; the split is a
+     * 16-bit fixed point, not a bf16 rounding).  Per column tile and row i,
+     * E_i is the exponent of 1.004 max |x| rounded up, each value's
+     * q = x 2^(15-E_i) is rounded to an integer (|q| < 32640) and split into
+     * two 8-bit integers, q = 256 hi + lo.  For extents up to 256 the four
+     * products hh, hl, lh, ll run on int8 matrix cores into three int32
+     * accumulators (hh; hl + lh; ll), for larger extents on bf16 matrix
+     * cores (both halves are exact in bf16) into three FP32 accumulators;
+     * either way the sums over a tile are exact, and after every tile they
+     * are combined exactly, scaled by 2^(E_i+E_j-30) and added into FP64.
+     * Each element is represented to 2^-16 of 2^E_i.  The quantization error d of every
      * element is formed exactly, and sum_k d_ik^2 is subtracted from S_ii:
      * quantization noise independent of the data adds its energy to the
      * Gram's diagonal, which would raise its trailing eigenvalue sums by

@@ -1,31 +1,29 @@
-// Mixed-precision kernels for FP32-stored tensors: the split-bf16 Gram and
-// the bf16 / split-bf16 TTM.  Neither changes what Alg. 1 computes; they
-// change the arithmetic of its two bulk steps (Gram, TTM) while the
+// Mixed-precision kernels for FP32-stored tensors: the split Gram and the
+// bf16 / split-bf16 TTM.  Neither changes what Alg. 1 computes; they change
+// the arithmetic of its two bulk steps (Gram, TTM) while the
 // eigendecomposition and the rank rule stay in FP64.
 //
-// Split-bf16 Gram.  The rank rule compares tail sums of eigenvalues with
+// Split Gram.  The rank rule compares tail sums of eigenvalues with
 // eps^2 ||X||^2 / N, so the Gram's error in the trailing eigenvalues must
 // stay far below that threshold.  Rounding inside the products would not
 // (dropping lo*lo, or rounding FP32 partial sums, leaves errors that do not
 // average out of the trailing eigenvalues).  Hence every product and sum on
-// the matrix cores is exact: per tile of KT columns and per row i with
-// max |x| < 2^E_i, s = x 2^(7 - E_i) is rounded to the grid 2^-8 (16-bit
-// fixed point) and split into two 8-bit halves
-//     hi = round(s)                        an integer in [-128, 128]
-//     lo = round(256 (s - hi)) / 256       256 lo an integer in [-128, 128]
-// both exact in bf16, and a 32x32 block of S = Y_(n) Y_(n)^T is
-//     2^(E_i + E_j - 14) (H_i H_j^T + [H_i L_j^T + L_i H_j^T] + L_i L_j^T)
-// on v_mfma_f32_32x32x16_bf16, the three terms in three FP32 accumulators:
-// over at most 128 columns each sum is an integer multiple of its quantum
-// (1, 2^-8, 2^-16) below 2^22 of it, so exact.  They are scaled and added
-// into FP64 registers after every tile.  What remains is the quantization
-// error d = s - hi - lo, |d| <= 2^-9, of every element: the split Gram is
-// exactly Y~ Y~^T with Y~ = Y - D.  Quantization noise independent of the
-// data adds its energy to the diagonal, so sum_k d_ik^2 (formed exactly
-// per element) is subtracted from S_ii; the rest of D's contribution has
-// mean zero (see EigArgs::guard for the model and the bound it gives).
-// Partials use the FP64 Gram's 16x16 pair layout and its fixed-order
-// reduction.
+// the matrix cores is exact: per tile of KT columns and per row i, every
+// element is rounded to 16-bit fixed point relative to 2^E_i (E_i from the
+// row's largest magnitude) and split into two 8-bit integer halves.  For
+// extents up to 256 (gram_s16_body) the halves are int8 operands of
+// v_mfma_i32_16x16x64_i8 with exact int32 sums; for 512 (gram_bf16s_body)
+// they are exact bf16 operands of v_mfma_f32_32x32x16_bf16, whose FP32 sums
+// over at most 128 columns are integer multiples of their quantum below 2^22
+// of it, so exact as well.  Either way the three sums (hi hi, hi lo + lo hi,
+// lo lo) are combined exactly, scaled and added into FP64 registers after
+// every tile.  What remains is the quantization error d, |d| <= 2^(E_i-16),
+// of every element: the split Gram is exactly Y~ Y~^T with Y~ = Y - D.
+// Quantization noise independent of the data adds its energy to the
+// diagonal, so sum_k d_ik^2 (formed exactly per element) is subtracted from
+// S_ii; the rest of D's contribution has mean zero (see EigArgs::guard for
+// the model and the bound it gives).  Partials use the FP64 Gram's 16x16
+// pair layout and its fixed-order reduction.
 //
 // bf16 TTM.  Z = op(M) Y with op(M) (K x J) split into bf16 hi/lo fragments
 // once per workgroup (in LDS) and Y split per element as it is loaded:
@@ -34,6 +32,7 @@
 // columns are contiguous (mode 1) every lane loads its eight consecutive
 // rows straight from HBM, no LDS staging needed.
 #include <algorithm>
+#include <type_traits>
 
 #include "tk_common.hpp"
 
@@ -50,7 +49,25 @@ constexpr int kMxThreads = 512;
 constexpr int kMxWaves = kMxThreads / 64;
 
 // Loader modes.
-enum { kUnit = 0, kContig = 1, kStrided = 2 };
+enum { kUnit = 0, kContig = 1, kStrided = 2, kUnit4 = 3 };
+
+// max of v over lanes l and l ^ OFF (OFF = 16, 32: permlane swaps; 4, 8:
+// rotation inside a 16-lane row, which after offsets 4 then 8 leaves every
+// lane the max of its residue class mod 4 in that row)
+template <int OFF>
+__device__ __forceinline__ float lane_fmax(float v) {
+    if constexpr (OFF == 32 || OFF == 16) {
+        const int b = __float_as_int(v);
+        const auto r = OFF == 32 ? __builtin_amdgcn_permlane32_swap(b, b, false, false)
+                                 : __builtin_amdgcn_permlane16_swap(b, b, false, false);
+        return __builtin_fmaxf(__int_as_float(r[0]), __int_as_float(r[1]));
+    } else {
+        static_assert(OFF == 4 || OFF == 8, "row rotations by 4 or 8");
+        const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + OFF, 0xf, 0xf,
+                                                  false);  // row_ror:OFF
+        return __builtin_fmaxf(v, __int_as_float(o));
+    }
+}
 
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_max(unsigned v) {
@@ -71,19 +88,30 @@ __device__ __forceinline__ unsigned dpp_max(unsigned v) {
 //            threads owns one row, thread t the column group t % (KT / 8);
 //            each group is two 16-byte loads.
 //   kStrided (otherwise): as kContig, one element per load.
-template <int JB, int KT, int MODE>
+//   kUnit4   (L == 1, J % 4 == 0, 16-byte aligned; JB >= 128): wave w owns
+//            rows [w JB/8, (w+1) JB/8); lane l holds the four consecutive
+//            rows 4 (l % QPW) of them for the eight columns 8 (l / QPW) + e,
+//            one 16-byte load per column (groups m = the four rows).
+template <int JB, int KT, int MODE, int NBUF = 1>
 struct SplitTile {
     static constexpr int PK = KT + 8;
     static constexpr int NCG = KT / 8;                              // groups per row
     static constexpr int RW = JB / kMxWaves > 16 ? JB / kMxWaves : 16;  // kUnit rows per wave
     static constexpr int LPR = 64 / RW;                             // kUnit lanes per row
     static constexpr int ROWSTEP = kMxThreads / NCG;                // strided rows per pass
-    static constexpr int NGRP = MODE == kUnit ? NCG / LPR : JB * NCG / kMxThreads;
+    static constexpr int QPW = JB / kMxWaves / 4;                   // kUnit4 row quads per wave
+    static constexpr int NGRP = MODE == kUnit4  ? 4
+                                : MODE == kUnit ? NCG / LPR
+                                                : JB * NCG / kMxThreads;
     static_assert(RW <= 64 && NCG % LPR == 0, "unit mapping");
-    static_assert(MODE == kUnit || (NGRP >= 1 && JB * NCG % kMxThreads == 0 && NCG <= 16),
+    static_assert(MODE == kUnit || MODE == kUnit4 ||
+                      (NGRP >= 1 && JB * NCG % kMxThreads == 0 && NCG <= 16),
                   "strided mapping");
+    static_assert(MODE != kUnit4 || (QPW >= 1 && 64 % QPW == 0 && KT == 8 * (64 / QPW)),
+                  "kUnit4 mapping: the wave's lanes cover its rows and the tile's columns");
 
-    float v[NGRP][8];
+    float vb[NBUF][NGRP][8];  // NBUF register tiles (loads of one in flight while another is split)
+    unsigned okm[NBUF];       // kUnit4: bit e set if column group element e is inside the tile
     int i0, cg0;
     bool owner;      // kUnit: this wave holds rows
     int coff[8];     // strided: offsets of the thread's 8 columns inside a tile
@@ -103,7 +131,12 @@ struct SplitTile {
 #pragma unroll
         for (int m = 0; m < NROW; ++m) rd[m] = 0.0;
         emax = -125;
-        if (MODE == kUnit) {
+        if (MODE == kUnit4) {
+            const int w = tid >> 6, l = tid & 63;
+            owner = true;
+            i0 = w * (JB / kMxWaves) + 4 * (l % QPW);
+            cg0 = l / QPW;
+        } else if (MODE == kUnit) {
             const int w = tid >> 6, l = tid & 63;
             owner = w * RW < JB;
             i0 = w * RW + l % RW;
@@ -117,16 +150,70 @@ struct SplitTile {
         }
     }
     __device__ __forceinline__ int row_of(int m) const {
-        return MODE == kUnit ? i0 : i0 + m * ROWSTEP;
+        return MODE == kUnit ? i0 : MODE == kUnit4 ? i0 + m : i0 + m * ROWSTEP;
     }
     __device__ __forceinline__ int cg_of(int m) const {
         return MODE == kUnit ? cg0 + m * LPR : cg0;
     }
 
+    // kUnit4, full tile t with J == JB (L == 1: the tile is the KT JB floats
+    // from t KT JB on).  Raw buffer loads: the tile's base goes into a scalar
+    // descriptor whose range is the tile, the lane's offset is fixed and the
+    // column step is a scalar offset, so no vector register is written to
+    // address the loads (a register written while an older load into it may
+    // be in flight would make the compiler wait for every load).
+    template <int B>
+    __device__ __forceinline__ void load_full(const float* __restrict__ y, int64_t t) {
+        static_assert(MODE == kUnit4, "full-tile loads: kUnit4 only");
+        float(&v)[NGRP][8] = vb[B];
+        okm[B] = 0xffu;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)uni(y + t * (int64_t)(KT * JB)), (short)0, KT * JB * (int)sizeof(float),
+            0x00020000);  // gfx9 word 3: 32-bit data format, untyped access
+        const int voff = (8 * cg0 * JB + i0) * (int)sizeof(float);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const f4_t x = __builtin_amdgcn_raw_buffer_load_b128(
+                rs, voff, e * JB * (int)sizeof(float), 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j][e] = x[j];
+        }
+    }
+
+    template <int B = 0>
     __device__ __forceinline__ void load(const float* __restrict__ y, const TileMap& tm,
                                          const Tile& t) {
+        float(&v)[NGRP][8] = vb[B];
         const int J = tm.J;
-        if (MODE == kUnit) {
+        if (MODE == kUnit4) {
+            // column kk = 8 cg0 + e holds rows i0..i0+3 at base + kk J + i0.
+            // Elements outside the tile come from clamped addresses and are
+            // zeroed when the tile is split, so no load result is used here.
+            if (t.ncols == KT && J == JB) {
+                okm[B] = 0xffu;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const f4_t x = *(const f4_t*)(y + t.base + (int64_t)(8 * cg0 + e) * JB + i0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j][e] = x[j];
+                }
+            } else {
+                // J % 4 == 0: a row quad is wholly in or out
+                const bool rok = i0 < J;
+                const int ic = rok ? i0 : J - 4;
+                unsigned mk = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int kk = 8 * cg0 + e;
+                    mk |= (rok && kk < t.ncols) ? 1u << e : 0u;
+                    const int kc = kk < t.ncols ? kk : t.ncols - 1;
+                    const f4_t x = *(const f4_t*)(y + t.base + (int64_t)kc * J + ic);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j][e] = x[j];
+                }
+                okm[B] = mk;
+            }
+        } else if (MODE == kUnit) {
             // element (i0, kk) with kk = 8 cg0 + [8 m LPR + e]: a wave-uniform
             // column part plus a fixed per-lane 32-bit offset
             const bool ok = owner && i0 < J;
@@ -165,9 +252,24 @@ struct SplitTile {
     }
 
     // Largest |x| of the row of group m over the whole tile (as float bits).
+    template <int B = 0>
     __device__ __forceinline__ unsigned row_max_bits(int m) const {
+        const float(&v)[NGRP][8] = vb[B];
         unsigned b = 0;
-        if (MODE == kUnit) {
+        if (MODE == kUnit4) {
+            // |x| maxima as floats (abs is a free operand modifier); NaN and
+            // Inf still reach the Gram through d = x 2^(15-E) - q
+            float f = __builtin_fmaxf(__builtin_fabsf(v[m][0]), __builtin_fabsf(v[m][1]));
+#pragma unroll
+            for (int e = 2; e < 8; e += 2)
+                f = __builtin_fmaxf(f, __builtin_fmaxf(__builtin_fabsf(v[m][e]),
+                                                       __builtin_fabsf(v[m][e + 1])));
+            if constexpr (QPW <= 4) f = lane_fmax<4>(f);
+            if constexpr (QPW <= 8) f = lane_fmax<8>(f);
+            if constexpr (QPW <= 16) f = lane_fmax<16>(f);
+            f = lane_fmax<32>(f);
+            b = __float_as_uint(f);
+        } else if (MODE == kUnit) {
 #pragma unroll
             for (int q = 0; q < NGRP; ++q)
 #pragma unroll
@@ -200,6 +302,7 @@ struct SplitTile {
     // FP32 (the bf16 rounding error of lo) and its square summed, rescaled
     // by 2^(2 (E-7)) per row.
     __device__ __forceinline__ void store(__bf16* hi, __bf16* lo, int* ex) {
+        const float(&v)[NGRP][8] = vb[0];
         unsigned mb = 0;
         if (MODE == kUnit) mb = row_max_bits(0);  // every group of the thread is one row
         float rs = 0.f;                            // kUnit: the row's scaled sum of d^2
@@ -248,10 +351,97 @@ struct SplitTile {
         }
     }
 
+    // The int8 form of the same 16-bit fixed point: per row, E is chosen with
+    // max |x| 2^(15-E) < 32640, so q = round(x 2^(15-E)) lies in
+    // [-32639, 32639] and splits as q = 256 hi + lo with
+    //     hi = (q + 128) >> 8 in [-128, 127],  lo = q - 256 hi in [-128, 127].
+    // Adding 1.5 2^23 + 128 to x 2^(15-E) rounds it to an integer (to
+    // nearest, ties to even) whose float bits end in the 16-bit two's
+    // complement of q + 128: byte 1 is hi, byte 0 xor 0x80 is lo.  The two
+    // int8 planes are [JB][KT + 16] bytes; each row's scale 2^(E-15) goes to
+    // sc[row] as a double.  d = x 2^(15-E) - q is formed exactly.
+    template <int B = 0>
+    __device__ __forceinline__ void store16(unsigned char* hi, unsigned char* lo, double* sc,
+                                            bool count = true) {
+        float(&v)[NGRP][8] = vb[B];
+        if (MODE == kUnit4 && okm[B] != 0xffu) {  // a partial tile: zero what lies outside
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = (okm[B] >> e) & 1u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j][e] = ok ? v[j][e] : 0.f;
+            }
+        }
+        constexpr int PKB = KT + 16;
+        constexpr float kMagic = 12583040.0f;  // 1.5 2^23 + 128
+        unsigned mb = 0;
+        if (MODE == kUnit) mb = row_max_bits<B>(0);
+        float rs = 0.f;
+        int sh = 0;
+#pragma unroll
+        for (int m = 0; m < NGRP; ++m) {
+            if (MODE != kUnit || m == 0) {
+                if (MODE != kUnit) mb = row_max_bits<B>(m);
+                // E: the exponent of max |x| (1 + 2^-8) rounded up, so that
+                // max |x| 2^(15-E) < 32768 / 1.004 < 32639.5; zero rows get
+                // the smallest normal exponent
+                const unsigned bb = __float_as_uint(__uint_as_float(mb) * 1.004f);
+                const int E = (int)(bb >> 23) - 126;
+                sh = 15 - (E < -125 ? -125 : E);
+            }
+            unsigned b[8];
+            float gs = 0.f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float sx = __builtin_ldexpf(v[m][e], sh);
+                const float f = sx + kMagic;
+                const float qf = f - kMagic;
+                const float dd = sx - qf;
+                gs = __builtin_fmaf(dd, dd, gs);
+                b[e] = __float_as_uint(f);
+            }
+            unsigned hw[2], lw[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // [lo'0, hi0, lo'1, hi1] and [lo'2, hi2, lo'3, hi3], lo' = lo ^ 0x80
+                const unsigned p01 = __builtin_amdgcn_perm(b[4 * h + 1], b[4 * h], 0x05040100u);
+                const unsigned p23 = __builtin_amdgcn_perm(b[4 * h + 3], b[4 * h + 2], 0x05040100u);
+                hw[h] = __builtin_amdgcn_perm(p23, p01, 0x07050301u);
+                lw[h] = __builtin_amdgcn_perm(p23, p01, 0x06040200u) ^ 0x80808080u;
+            }
+            const int r = row_of(m);
+            const bool mine = MODE != kUnit || owner;
+            if (mine) {
+                const int off = r * PKB + 8 * cg_of(m);
+                *(uint2*)(hi + off) = make_uint2(hw[0], hw[1]);
+                *(uint2*)(lo + off) = make_uint2(lw[0], lw[1]);
+                if (cg_of(m) == 0) sc[r] = __builtin_ldexp(1.0, -sh);
+            }
+            if (MODE == kUnit) {
+                rs += gs;
+            } else if (r < JB && count) {
+                rd[m] += __builtin_ldexp((double)gs, -2 * sh);
+                emax = max(emax, 15 - sh);
+            }
+        }
+        if (MODE == kUnit && owner && count) {
+            rd[0] += __builtin_ldexp((double)rs, -2 * sh);
+            emax = max(emax, 15 - sh);
+        }
+    }
+
     // Per-row sums of d^2 over the workgroup into rowd[0..JB) (each row's
     // holders form a fixed xor-butterfly; rows nobody holds stay as set).
     __device__ __forceinline__ void row_sums(double* rowd, int lane) const {
-        if (MODE == kUnit) {
+        if (MODE == kUnit4) {
+#pragma unroll
+            for (int m = 0; m < NROW; ++m) {
+                double v = rd[m];
+#pragma unroll
+                for (int d = QPW; d < 64; d *= 2) v += __shfl_xor(v, d);
+                if (cg0 == 0 && i0 + m < JB) rowd[i0 + m] = v;
+            }
+        } else if (MODE == kUnit) {
             double v = rd[0];
 #pragma unroll
             for (int d = RW; d < 64; d *= 2) v += __shfl_xor(v, d);
@@ -452,6 +642,273 @@ __device__ __forceinline__ void gram_bf16s_body(
     if (aux) split_stats_out(ld.total(), ld.emax, aux, lds_raw);  // uniform branch
 }
 
+// ---- the same split on int8 matrix cores (extents up to 256) ----------
+//
+// A 16x16 block of S is
+//     sum_k q_ik q_jk 2^(E_i + E_j - 30)
+//       = 2^(E_i + E_j - 30) (65536 HH + 256 [HL + LH] + LL)
+// with HH = sum hi_i hi_j etc.: v_mfma_i32_16x16x64_i8 forms the three sums
+// exactly in int32 (|HH| <= 2^14 KT, |HL + LH| <= 2^15 KT, KT <= 256), and
+// after every tile 256 HH + (HL + LH) (below 2^31) and LL are converted and
+// combined exactly in FP64, scaled by the two row scales and added.  The
+// 16-block pairs (bi <= bj) of the workgroup's pair group are dealt to the
+// waves in a snake order (q even: wave w, q odd: wave 7 - w), which balances
+// the SIMDs (waves w and w + 4 share one) when a group has 36 pairs.
+typedef int i4v_t __attribute__((ext_vector_type(4)));
+
+// Extent 128 (8 blocks of 16, 36 pairs): a fixed schedule per wave whose
+// pairs share blocks, so that each wave reads every block's fragments once
+// per k-step (at most 5 blocks, 140 KB of fragment reads per tile instead of
+// 288 KB with 4 per pair).  Waves w < 4 take row w's pairs (w, w..w+4);
+// wave w + 4 the rest of row w and all of row 7 - w.  Waves w and w + 4 share
+// a SIMD and hold 9 pairs between them.
+struct WaveSched {
+    int nblk, blk[5];         // blocks whose fragments the wave reads
+    int npair, pa[5], pb[5];  // pair q = (blk[pa[q]], blk[pb[q]])
+};
+constexpr WaveSched kSched128[8] = {
+    {5, {0, 1, 2, 3, 4}, 5, {0, 0, 0, 0, 0}, {0, 1, 2, 3, 4}},
+    {5, {1, 2, 3, 4, 5}, 5, {0, 0, 0, 0, 0}, {0, 1, 2, 3, 4}},
+    {5, {2, 3, 4, 5, 6}, 5, {0, 0, 0, 0, 0}, {0, 1, 2, 3, 4}},
+    {5, {3, 4, 5, 6, 7}, 5, {0, 0, 0, 0, 0}, {0, 1, 2, 3, 4}},
+    {4, {0, 5, 6, 7, 0}, 4, {0, 0, 0, 3, 0}, {1, 2, 3, 3, 0}},  // (0,5) (0,6) (0,7) (7,7)
+    {3, {1, 6, 7, 0, 0}, 4, {0, 0, 1, 1, 0}, {1, 2, 1, 2, 0}},  // (1,6) (1,7) (6,6) (6,7)
+    {4, {2, 5, 6, 7, 0}, 4, {0, 1, 1, 1, 0}, {3, 1, 2, 3, 0}},  // (2,7) (5,5) (5,6) (5,7)
+    {4, {4, 5, 6, 7, 0}, 4, {0, 0, 0, 0, 0}, {0, 1, 2, 3, 0}},  // (4,4) (4,5) (4,6) (4,7)
+};
+
+template <int JB, int KT>
+constexpr size_t s16_buf_bytes() {
+    return ((size_t)2 * JB * (KT + 16) + (size_t)JB * sizeof(double) + 15) / 16 * 16;
+}
+
+// NBUF = 2 keeps two register tiles: tile t + 2 loads while tile t is on
+// the matrix cores and tile t + 1 is split, so every load has about two
+// iterations to arrive.  Its loads are unconditional (past the range end the
+// last tile is loaded again and split without counting its statistics).
+template <int JB, int KT, int NPW, int MODE, int NBUF = 1>
+__device__ __forceinline__ void gram_s16_body(
+    const float* __restrict__ y, const TileMap& tm, int npairs16, int pairs_per_group, int group,
+    int64_t t0, int64_t t1, double* __restrict__ out, double* aux, double* lds_raw) {
+    using Ld = SplitTile<JB, KT, MODE, NBUF>;
+    constexpr int PKB = KT + 16;
+    constexpr int PLANE = JB * PKB;
+    constexpr size_t BUF = s16_buf_bytes<JB, KT>();
+    constexpr int NKS = KT / 64;
+    constexpr int NB = JB / 16;
+    static_assert(KT % 64 == 0 && KT <= 256, "k-steps of 64; int32 sums exact for KT <= 256");
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // pair choices stay scalar
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int g0 = group * pairs_per_group;
+
+    constexpr bool kSched = JB == 128;  // the fixed per-wave schedule above
+    static_assert(!kSched || NPW == 5, "the extent-128 schedule has up to 5 pairs per wave");
+    int bi[NPW], bj[NPW], aoff[NPW], boff[NPW];
+    bool act[NPW];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        if constexpr (kSched) {
+            const WaveSched& ws = kSched128[wave];
+            act[q] = q < ws.npair;
+            bi[q] = ws.blk[ws.pa[q]];
+            bj[q] = ws.blk[ws.pb[q]];
+        } else {
+            const int pl = q * kMxWaves + ((q & 1) ? kMxWaves - 1 - wave : wave);
+            const int p = g0 + pl;
+            act[q] = pl < pairs_per_group && p < npairs16;
+            pair32_of(act[q] ? p : 0, NB, bi[q], bj[q]);  // the upper-triangle order, NB blocks
+        }
+        aoff[q] = (16 * bi[q] + r16) * PKB + 16 * kq;
+        boff[q] = (16 * bj[q] + r16) * PKB + 16 * kq;
+    }
+
+    double accd[NPW][4];
+#pragma unroll
+    for (int q = 0; q < NPW; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[q][v] = 0.0;
+
+    char* base = (char*)lds_raw;
+    auto hi_of = [&](int b) { return (unsigned char*)(base + b * BUF); };
+    auto sc_of = [&](int b) { return (double*)(base + b * BUF + 2 * PLANE); };
+
+    // flush of pair q's exact int32 sums into its FP64 accumulators
+    // (v_mfma_i32_16x16x64 output: row 4 (lane / 16) + v, column lane % 16)
+    auto flush = [&](int q, const i4v_t& hh, const i4v_t& mm, const i4v_t& ll, const double* sc) {
+        const double sj = sc[16 * bj[q] + r16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double si = sc[16 * bi[q] + 4 * kq + v];
+            const double c1 = (double)(hh[v] * 256 + mm[v]);
+            const double tv = __builtin_fma(c1, 256.0, (double)ll[v]);
+            accd[q][v] = __builtin_fma(tv * si, sj, accd[q][v]);
+        }
+    };
+    // the scheduled waves: fragments of each block read once per k-step
+    auto mfma_sched = [&](auto wc, const unsigned char* hb, const unsigned char* lb,
+                          const double* sc) {
+        constexpr WaveSched ws = kSched128[decltype(wc)::value];
+        i4v_t acc[5][3];
+#pragma unroll
+        for (int q = 0; q < ws.npair; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[q][c] = i4v_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            i4v_t fh[5], fl[5];
+#pragma unroll
+            for (int b = 0; b < ws.nblk; ++b) {
+                const int off = (16 * ws.blk[b] + r16) * PKB + 16 * kq + 64 * ks;
+                fh[b] = *(const i4v_t*)(hb + off);
+                fl[b] = *(const i4v_t*)(lb + off);
+            }
+#pragma unroll
+            for (int q = 0; q < ws.npair; ++q) {
+                const int a = ws.pa[q], c = ws.pb[q];
+                acc[q][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fh[a], fh[c], acc[q][0], 0, 0, 0);
+                acc[q][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fh[a], fl[c], acc[q][1], 0, 0, 0);
+                acc[q][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fl[a], fh[c], acc[q][1], 0, 0, 0);
+                acc[q][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fl[a], fl[c], acc[q][2], 0, 0, 0);
+            }
+            // one k-step's fragments live at a time
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int q = 0; q < ws.npair; ++q) flush(q, acc[q][0], acc[q][1], acc[q][2], sc);
+    };
+    // all block pairs of the wave on the tile in LDS buffer b
+    auto mfma_tile = [&](int b) {
+        const unsigned char* hb = hi_of(b);
+        const unsigned char* lb = hb + PLANE;
+        const double* sc = sc_of(b);
+        if constexpr (kSched) {
+            switch (wave) {  // uniform
+                case 0: mfma_sched(std::integral_constant<int, 0>{}, hb, lb, sc); break;
+                case 1: mfma_sched(std::integral_constant<int, 1>{}, hb, lb, sc); break;
+                case 2: mfma_sched(std::integral_constant<int, 2>{}, hb, lb, sc); break;
+                case 3: mfma_sched(std::integral_constant<int, 3>{}, hb, lb, sc); break;
+                case 4: mfma_sched(std::integral_constant<int, 4>{}, hb, lb, sc); break;
+                case 5: mfma_sched(std::integral_constant<int, 5>{}, hb, lb, sc); break;
+                case 6: mfma_sched(std::integral_constant<int, 6>{}, hb, lb, sc); break;
+                default: mfma_sched(std::integral_constant<int, 7>{}, hb, lb, sc); break;
+            }
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            if (!act[q]) continue;
+            i4v_t hh = {0, 0, 0, 0}, mm = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const i4v_t ah = *(const i4v_t*)(hb + aoff[q] + 64 * ks);
+                const i4v_t al = *(const i4v_t*)(lb + aoff[q] + 64 * ks);
+                const i4v_t bh = *(const i4v_t*)(hb + boff[q] + 64 * ks);
+                const i4v_t bl = *(const i4v_t*)(lb + boff[q] + 64 * ks);
+                hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bh, hh, 0, 0, 0);
+                mm = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bl, mm, 0, 0, 0);
+                mm = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bh, mm, 0, 0, 0);
+                ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bl, ll, 0, 0, 0);
+            }
+            flush(q, hh, mm, ll, sc);
+        }
+    };
+
+    Ld ld;
+    ld.setup(tm, tid);
+    if constexpr (NBUF == 1) {
+        if (t0 < t1) {
+            ld.load(y, tm, tile_at(tm, t0, tm.J));
+            ld.store16(hi_of(0), hi_of(0) + PLANE, sc_of(0));
+        }
+        __syncthreads();
+        for (int64_t t = t0; t < t1; ++t) {
+            const int cur = (int)((t - t0) & 1);
+            const bool more = t + 1 < t1;
+            if (more) ld.load(y, tm, tile_at(tm, t + 1, tm.J));  // in flight during the MFMAs
+            mfma_tile(cur);
+            if (more) {
+                const int nb2 = cur ^ 1;
+                ld.store16(hi_of(nb2), hi_of(nb2) + PLANE, sc_of(nb2));
+            }
+            __syncthreads();
+        }
+    } else {
+        // Two register tiles; only for kUnit4 with J == JB, where every tile
+        // but the tensor's last is full.  The loop runs over the full tiles
+        // [t0, tf) with loads clamped to tf - 1 and no branch around them; a
+        // ragged last tile follows on its own.
+        static_assert(NBUF == 2 && MODE == kUnit4, "two register tiles: kUnit4 only");
+        // tile counters relative to t0 in 32 bits (a workgroup's range is far
+        // below 2^31 tiles), so that every comparison stays scalar
+        int nf = (int)(t1 - t0);
+        if (nf > 0 && tile_at(tm, t1 - 1, tm.J).ncols < KT) --nf;
+        auto tile = [&](int r) { return t0 + (r < nf ? r : nf - 1); };
+        if (nf > 0) {  // uniform
+            ld.template load_full<0>(y, tile(0));
+            ld.template store16<0>(hi_of(0), hi_of(0) + PLANE, sc_of(0));
+            ld.template load_full<1>(y, tile(1));
+            __syncthreads();
+            int r = 0;
+            for (;;) {
+                // LDS buffer 0: tile r; registers 1: tile r + 1 (loaded)
+                ld.template load_full<0>(y, tile(r + 2));
+                mfma_tile(0);
+                ld.template store16<1>(hi_of(1), hi_of(1) + PLANE, sc_of(1), r + 1 < nf);
+                __syncthreads();
+                if (++r >= nf) break;
+                ld.template load_full<1>(y, tile(r + 2));
+                mfma_tile(1);
+                ld.template store16<0>(hi_of(0), hi_of(0) + PLANE, sc_of(0), r + 1 < nf);
+                __syncthreads();
+                if (++r >= nf) break;
+            }
+        }
+        if (t0 + nf < t1) {  // the ragged last tile
+            ld.template load<0>(y, tm, tile_at(tm, t1 - 1, tm.J));
+            ld.template store16<0>(hi_of(0), hi_of(0) + PLANE, sc_of(0));
+            __syncthreads();
+            mfma_tile(0);
+        }
+        __syncthreads();
+    }
+
+    // subtract each row's sum of d^2 from its diagonal entry (as the bf16 body)
+    double* rowd = lds_raw + 64;
+    for (int i = tid; i < JB; i += kMxThreads) rowd[i] = 0.0;
+    __syncthreads();
+    ld.row_sums(rowd, lane);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+        if (!act[q]) continue;
+        const int p16 = bi[q] * NB - bi[q] * (bi[q] - 1) / 2 + (bj[q] - bi[q]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int il = 4 * kq + v;
+            const bool dg = bi[q] == bj[q] && il == r16;
+            out[(int64_t)p16 * 256 + il * 16 + r16] =
+                dg ? accd[q][v] - rowd[16 * bi[q] + il] : accd[q][v];
+        }
+    }
+    if (aux) split_stats_out(ld.total(), ld.emax, aux, lds_raw);  // uniform branch
+}
+
+template <int JB, int KT, int NPW, int MODE, int NBUF>
+__global__ __launch_bounds__(kMxThreads) void gram_partial_s16(
+    const float* __restrict__ y, TileMap tm, int npairs16, int pairs_per_group, int P, int G,
+    double* __restrict__ partial) {
+    extern __shared__ double lds_raw[];
+    int p, g;
+    xcd_range_group(blockIdx.x, G, p, g);
+    const int64_t t0 = tm.ntiles * (int64_t)p / P;
+    const int64_t t1 = tm.ntiles * (int64_t)(p + 1) / P;
+    double* aux = g == 0 ? partial + (int64_t)P * npairs16 * 256 + 2 * p : nullptr;
+    gram_s16_body<JB, KT, NPW, MODE, NBUF>(y, tm, npairs16, pairs_per_group, g, t0, t1,
+                                           partial + (int64_t)p * npairs16 * 256, aux, lds_raw);
+}
+
 // P tile ranges x G pair groups, one workgroup each (xcd_range_group).  The
 // P x 2 split statistics follow the P partials; pair group 0 writes them.
 template <int JB, int KT, int NPW, int MODE>
@@ -469,17 +926,26 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
 }
 
 // Static schedule per padded extent: tile width, pairs per wave, pair groups
-// (each re-reads the tensor), workgroups per CU.
+// (each re-reads the tensor), workgroups per CU.  Extents up to 256 run the
+// int8 kernel on 16-block pairs, 512 the bf16 kernel on 32-block pairs.
 struct MxGramShape {
     int KT, NPW, G, per_cu;
 };
 template <int JB>
+constexpr bool mx_int8() {
+    return JB <= 256;
+}
+template <int JB>
 constexpr MxGramShape mx_gram_shape() {
-    return JB == 32    ? MxGramShape{128, 1, 1, 2}   //   1 pair
-           : JB == 64  ? MxGramShape{128, 1, 1, 2}   //   3 pairs
-           : JB == 128 ? MxGramShape{128, 2, 1, 1}   //  10 pairs over 8 waves
-           : JB == 256 ? MxGramShape{64, 2, 3, 1}    //  36 pairs: 3 groups of 12
-                       : MxGramShape{16, 2, 9, 1};   // 136 pairs: 9 groups of 16
+    return JB == 32    ? MxGramShape{128, 1, 1, 2}   //   3 16-pairs
+           : JB == 64  ? MxGramShape{128, 2, 1, 2}   //  10 16-pairs
+           : JB == 128 ? MxGramShape{128, 5, 1, 1}   //  36 16-pairs, 9 per SIMD
+           : JB == 256 ? MxGramShape{64, 6, 3, 1}    // 136 16-pairs: 3 groups of 46
+                       : MxGramShape{16, 2, 9, 1};   // 136 32-pairs: 9 groups of 16
+}
+template <int JB>
+constexpr int mx_owned_pairs() {  // pairs the kernel's owner waves are dealt
+    return mx_int8<JB>() ? (JB / 16) * (JB / 16 + 1) / 2 : (JB / 32) * (JB / 32 + 1) / 2;
 }
 
 static int mx_round_jb(int J) {
@@ -491,17 +957,15 @@ static int mx_round_jb(int J) {
 template <int JB>
 static GramPlan mx_plan(const ModeView& v) {
     constexpr MxGramShape gs = mx_gram_shape<JB>();
-    static_assert(kMxWaves * gs.NPW * gs.G >= JB / 32 * (JB / 32 + 1) / 2 &&
-                      kMxWaves * gs.NPW >= (JB / 32 * (JB / 32 + 1) / 2 + gs.G - 1) / gs.G,
+    constexpr int owned = mx_owned_pairs<JB>();
+    static_assert(kMxWaves * gs.NPW >= (owned + gs.G - 1) / gs.G,
                   "every pair of a group needs an owner wave");
     GramPlan pl{};
     TileMap tm = make_tiles(v, gs.KT);
-    const int nb32 = JB / 32;
-    const int npairs32 = nb32 * (nb32 + 1) / 2;
     pl.KT = gs.KT;
     pl.G = gs.G;
-    pl.pairs_per_group = (npairs32 + gs.G - 1) / gs.G;
-    pl.nb = 2 * nb32;  // 16-blocks, for the shared reduction
+    pl.pairs_per_group = (owned + gs.G - 1) / gs.G;
+    pl.nb = JB / 16;  // 16-blocks, for the shared reduction
     pl.npairs = pl.nb * (pl.nb + 1) / 2;
     const int64_t want = xcd_round_want((int64_t)gs.per_cu * device_cu_count() / pl.G, pl.G);
     pl.P = xcd_ranges(tm.ntiles, want, pl.G);
@@ -521,17 +985,27 @@ GramPlan plan_gram_mixed(const ModeView& v) {
     }
 }
 
-template <int JB, int MODE>
+template <int JB, int MODE, int NBUF = 1>
 static int mx_launch(const float* y, const TileMap& tm, const GramPlan& pl, double* partial,
                      hipStream_t st) {
     constexpr MxGramShape gs = mx_gram_shape<JB>();
-    auto fn = gram_partial_bf16s<JB, gs.KT, gs.NPW, MODE>;
-    const size_t lds = 2 * mx_buf_bytes<JB, gs.KT>();
-    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    const int nb32 = JB / 32;
-    hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kMxThreads), lds, st, y, tm,
-                       nb32 * (nb32 + 1) / 2, pl.pairs_per_group, pl.npairs, pl.P, pl.G, partial);
+    if constexpr (mx_int8<JB>()) {
+        auto fn = gram_partial_s16<JB, gs.KT, gs.NPW, MODE, NBUF>;
+        const size_t lds = 2 * s16_buf_bytes<JB, gs.KT>();
+        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kMxThreads), lds, st, y, tm, pl.npairs,
+                           pl.pairs_per_group, pl.P, pl.G, partial);
+    } else {
+        auto fn = gram_partial_bf16s<JB, gs.KT, gs.NPW, MODE>;
+        const size_t lds = 2 * mx_buf_bytes<JB, gs.KT>();
+        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        const int nb32 = JB / 32;
+        hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kMxThreads), lds, st, y, tm,
+                           nb32 * (nb32 + 1) / 2, pl.pairs_per_group, pl.npairs, pl.P, pl.G,
+                           partial);
+    }
     TK_HIP(hipGetLastError());
     return TK_OK;
 }
@@ -540,22 +1014,41 @@ template <int JB>
 static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& pl,
                             double* partial, hipStream_t st) {
     TileMap tm = make_tiles(v, pl.KT);
+    if constexpr (JB == 128 || JB == 256) {
+        if (v.L == 1 && v.J % 4 == 0 && ((uintptr_t)y & 15) == 0)
+            return v.J == JB ? mx_launch<JB, kUnit4, 2>(y, tm, pl, partial, st)
+                             : mx_launch<JB, kUnit4, 1>(y, tm, pl, partial, st);
+    }
     if (v.L == 1) return mx_launch<JB, kUnit>(y, tm, pl, partial, st);
     const bool contig = v.L % 8 == 0 && ((uintptr_t)y & 15) == 0;
     if (contig) return mx_launch<JB, kContig>(y, tm, pl, partial, st);
     return mx_launch<JB, kStrided>(y, tm, pl, partial, st);
 }
 
-// ---- batches: one launch covers every problem of a batch ----------------
-template <int JB>
+// ---- batches: three launches cover every problem of a batch -------------
+// A problem's unfolding stride L depends on ranks found on the device, so
+// the three loader variants (L == 1; L % 8 == 0 with 16-byte alignment; any
+// other) run over the same task table, each returning at once for the tasks
+// of the others (one variant per kernel keeps each kernel's registers those
+// of its own loader).
+__device__ __forceinline__ int batch_loader(const ModeView& mv, const float* y) {
+    return mv.L == 1 ? kUnit : (mv.L % 8 == 0 && ((uintptr_t)y & 15) == 0) ? kContig : kStrided;
+}
+
+template <int JB, int MODE>
 __global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
     const BatchGramTask* __restrict__ tasks, int ntasks) {
     extern __shared__ double lds_raw[];
     constexpr MxGramShape gs = mx_gram_shape<JB>();
-    const int ti = find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x);
-    const BatchGramTask tk = tasks[ti];
-    const int w = blockIdx.x - tk.v.wg_begin;
-    const ModeView mv = batch_mode_view(tk.v);
+    const int ti = uni(find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x));
+    BatchGramTask tk = tasks[ti];
+    tk.y = uni(tk.y);
+    tk.partial = uni(tk.partial);
+    tk.aux = uni(tk.aux);
+    tk.tpw = uni(tk.tpw);
+    const int w = blockIdx.x - uni(tk.v.wg_begin);
+    const ModeView mv = uni(batch_mode_view(tk.v));
+    if (batch_loader(mv, tk.y) != MODE) return;  // uniform: another launch's task
     const TileMap tm = make_tiles(mv, gs.KT);
     // workgroups needed at the actual shape (>= 1: a shape has >= 1 tile)
     const int64_t need = (tm.ntiles + tk.tpw - 1) / tk.tpw;
@@ -564,18 +1057,11 @@ __global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
     if (w >= active) return;  // uniform over the workgroup
     const int64_t t0 = tm.ntiles * (int64_t)w / active;
     const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / active;
-    constexpr int nb32 = JB / 32, np32 = nb32 * (nb32 + 1) / 2, np16 = 2 * nb32 * (2 * nb32 + 1) / 2;
+    constexpr int np16 = (JB / 16) * (JB / 16 + 1) / 2;
+    static_assert(mx_int8<JB>(), "batches run the int8 kernel");
     double* out = tk.partial + (int64_t)w * np16 * 256;
     double* aux = tk.aux + 2 * w;
-    if (mv.L == 1)
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kUnit>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
-                                                  aux, lds_raw);
-    else if (mv.L % 8 == 0 && ((uintptr_t)tk.y & 15) == 0)
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kContig>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
-                                                    aux, lds_raw);
-    else
-        gram_bf16s_body<JB, gs.KT, gs.NPW, kStrided>(tk.y, tm, np32, np32, np16, 0, t0, t1, out,
-                                                     aux, lds_raw);
+    gram_s16_body<JB, gs.KT, gs.NPW, MODE>(tk.y, tm, np16, np16, 0, t0, t1, out, aux, lds_raw);
 }
 
 int mx_gram_kt(int jb) {
@@ -592,12 +1078,14 @@ template <int JB>
 static int launch_bf16s_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
                                   hipStream_t st) {
     static_assert(mx_gram_shape<JB>().G == 1, "batches need a single pair group");
-    auto fn = gram_bf16s_batched<JB>;
-    const size_t lds = 2 * mx_buf_bytes<JB, mx_gram_shape<JB>().KT>();
-    TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kMxThreads), lds, st, tasks, ntasks);
-    TK_HIP(hipGetLastError());
+    const size_t lds = 2 * s16_buf_bytes<JB, mx_gram_shape<JB>().KT>();
+    for (const auto fn : {gram_bf16s_batched<JB, kUnit>, gram_bf16s_batched<JB, kContig>,
+                          gram_bf16s_batched<JB, kStrided>}) {
+        TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kMxThreads), lds, st, tasks, ntasks);
+        TK_HIP(hipGetLastError());
+    }
     return TK_OK;
 }
 

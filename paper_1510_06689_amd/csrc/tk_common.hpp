@@ -334,6 +334,27 @@ inline int xcd_ranges(int64_t ntiles, int64_t want, int G) {
     return (int)p;
 }
 
+// Values the compiler cannot prove wave-uniform (a task table entry found by
+// a search, extents read from device memory) but that are: moved to scalar
+// registers, so that everything derived from them stays there too.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+    return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+__device__ __forceinline__ ModeView uni(const ModeView& v) {
+    ModeView u;
+    u.L = uni(v.L);
+    u.J = uni(v.J);
+    u.B = uni(v.B);
+    return u;
+}
+
 // Task of workgroup `wg` in a launch whose tasks (stride bytes apart, each
 // starting with a BatchView) own consecutive workgroup ranges.
 __device__ __forceinline__ int find_task_wg(const BatchView* v0, size_t stride, int ntasks,

@@ -52,17 +52,24 @@ def mode1_rows(x, i, j):
     return out
 
 
+# The split Gram's quantum for a row with largest magnitude m is at most
+# SPLIT_STEP 2^-14 m: its exponent is that of 1.004 m rounded up.
+SPLIT_STEP = 1.004
+
+
 def split_gram_bound(sub):
-    """Elementwise bound of the split-bf16 Gram (mode 1) of a row slice:
-    2^-15 (m_i |x_j|_1 + m_j |x_i|_1) + 2^-30 K m_i m_j (16-bit fixed-point
-    representation to 2^-15 m_i, exact products, the diagonal of D D^T
-    subtracted)."""
+    """Elementwise bound of the split Gram (mode 1) of a row slice:
+    c 2^-15 (m_i |x_j|_1 + m_j |x_i|_1) + c^2 2^-30 K m_i m_j, c = SPLIT_STEP
+    (16-bit fixed-point representation to c 2^-15 m_i, exact products, the
+    diagonal of D D^T subtracted)."""
     import oracle
     m = oracle.unfold(sub, 0)
     rmax = np.abs(m).max(axis=1)
     l1 = np.abs(m).sum(axis=1)
     k = m.shape[1]
-    return 2.0**-15 * (np.outer(rmax, l1) + np.outer(l1, rmax)) + 2.0**-30 * k * np.outer(rmax, rmax)
+    c = SPLIT_STEP
+    return (c * 2.0**-15 * (np.outer(rmax, l1) + np.outer(l1, rmax))
+            + c * c * 2.0**-30 * k * np.outer(rmax, rmax))
 
 
 # Relative error per element of one TTM's output, by arithmetic (taken as a

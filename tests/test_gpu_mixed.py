@@ -3,13 +3,14 @@ the same FP32-stored values (widened exactly to FP64).
 
 Tolerances are worst-case bounds of the split arithmetic, not fitted:
 
-* split-bf16 Gram: per tile and row, s = x 2^(7-E) is rounded to the grid
-  2^-8 and split into 8-bit halves, x = x~ + d with |d| <= 2^(E-16), where
-  max|x| < 2^E <= 2 max|x|; so every element is represented to 2^-15 m_i
-  (m_i the row's largest magnitude).  The products of the halves are exact
-  and sum_k d_ik^2 is subtracted from the diagonal, so S~ - S =
-  -(X D^T + D X^T) + offdiag(D D^T):
-      |dS_ij| <= 2^-15 (m_i |x_j|_1 + m_j |x_i|_1) + 2^-30 K m_i m_j.
+* split Gram: per tile and row, q = x 2^(15-E) is rounded to an integer
+  and split into 8-bit halves, x = x~ + d with |d| <= 2^(E-16), where E is
+  the exponent of 1.004 max|x| rounded up (so that |q| < 32640 fits the two
+  int8 halves): 2^E <= 2 * 1.004 max|x|, and every element is represented
+  to c 2^-15 m_i with c = 1.004 (m_i the row's largest magnitude).  The
+  products of the halves are exact and sum_k d_ik^2 is subtracted from the
+  diagonal, so S~ - S = -(X D^T + D X^T) + offdiag(D D^T):
+      |dS_ij| <= c 2^-15 (m_i |x_j|_1 + m_j |x_i|_1) + c^2 2^-30 K m_i m_j.
   Exact rank agreement on planted tensors is the sharper check.
 * split-bf16 TTM: x = hi + lo + d with |d| <= 2^-16 |x| on both operands,
   three products; plain bf16 TTM: |a_h y_h - a y| <= (2^-7 + 2^-16) |a y|;
@@ -24,7 +25,7 @@ import torch
 import oracle
 import synth
 from paper_1510_06689_amd import tucker
-from gpu_util import U32, U64, check_against_oracle, say, to_dev, to_host
+from gpu_util import SPLIT_STEP, U32, U64, check_against_oracle, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -36,8 +37,9 @@ def split_gram_tolerance(xh, n, ref):
     l1 = np.abs(m).sum(axis=1)
     k = m.shape[1]
     d = np.sqrt(np.abs(np.diag(ref)))
-    return (2.0**-15 * (np.outer(rowmax, l1) + np.outer(l1, rowmax))
-            + 2.0**-30 * k * np.outer(rowmax, rowmax)
+    c = SPLIT_STEP
+    return (c * 2.0**-15 * (np.outer(rowmax, l1) + np.outer(l1, rowmax))
+            + c * c * 2.0**-30 * k * np.outer(rowmax, rowmax)
             + (k + 2) * U64 * np.outer(d, d) + 1e-300)
 
 
