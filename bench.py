@@ -644,7 +644,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic("gram_split_bf16_combustion128"),
-                "kernel": "gram_partial_bf16s (mode 1, J=128, FP32 input)",
+                "kernel": "gram_partial_s16 (mode 1, J=128, FP32 input, int8 matrix cores)",
                 "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": k["gram_ms"]}
     else:
         flops = gram_flops(w.dims[0], x.numel())

@@ -382,8 +382,9 @@ size_t error_metrics_workspace_bytes(const tk_shape* x);
  * Many independent problems (each an ST-HOSVD as in sthosvd_compress; the
  * problems may have different extents) compressed together: every mode step
  * of every problem runs in a handful of launches that cover the whole batch
- * (a split-bf16 Gram, its reduction, one eigensolver workgroup per problem,
- * the guard's FP64 recomputation, a split-bf16 TTM), with each problem's
+ * (a split Gram -- for extents up to 32 the FP64 Gram, as sthosvd_compress
+ * does for narrow modes --, its reduction, one eigensolver workgroup per
+ * problem, the guard's FP64 recomputation, a bf16 or split-bf16 TTM), with each problem's
  * later shapes derived on the device from the ranks found there.  sthosvd_batch_run therefore enqueues work
  * without any host synchronisation, allocation or memset: it can be captured
  * into a HIP graph once and replayed.

@@ -2,8 +2,10 @@
 // planning, the enqueue-only run (graph-capturable) and the finishing step.
 //
 // Every mode step s of the common mode order runs, for the whole batch, as
-//   split-bf16 Gram  (one launch per padded-extent class, workgroups dealt
-//                     to problems in proportion to their capacity-size tiles)
+//   split Gram       (one launch per padded-extent class, workgroups dealt
+//                     to problems in proportion to their capacity-size tiles;
+//                     the class of extents up to 32 takes the FP64 Gram
+//                     instead, which costs no more there and needs no guard)
 //   reduction        (one launch; step 0 also forms ||X||^2 per problem)
 //   eigensolver      (one workgroup per problem, rank rule and guard on the
 //                     device)
@@ -31,7 +33,13 @@ namespace {
 struct GramLaunch {
     int jb, ntasks, total_wg;
     size_t off;  // byte offset of its tasks in the table area
+    bool f64;    // FP64 Gram (extents up to 32), else the split Gram
 };
+
+// Extent classes whose Gram runs in FP64 arithmetic: at J <= 32 the FP64
+// Gram's intensity on FP32 data is below the FP64 matrix-core ridge, so it
+// costs no more than the split Gram, and its rank needs no guard.
+bool f64_class(int jb) { return jb <= 32; }
 struct TtmLaunch {
     int J, kmax, ntasks, total_wg;
     size_t off;
@@ -232,10 +240,11 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
                              bufs[b].nparts, ceil_div(ntiles, nwg)};
             gt.v.nwg = nwg;
             gclass[jb].push_back(gt);
+            const bool f64 = f64_class(jb);
             BatchReduceTask rt{bufs[b].partial, bufs[b].S,
-                               s == 0 && h ? h->norm2_dev + b : nullptr, bufs[b].aux,
-                               bufs[b].stats, nwg, np16, nb16, v.J, 0, 0, status,
-                               bufs[b].nparts};
+                               s == 0 && h ? h->norm2_dev + b : nullptr,
+                               f64 ? nullptr : bufs[b].aux, f64 ? nullptr : bufs[b].stats, nwg,
+                               np16, nb16, v.J, 0, 0, status, bufs[b].nparts};
             // one more workgroup: split statistics, and at step 0 the trace
             rt.nwg = ceil_div((int64_t)np16 * 256, 64) + 1;
             rt.wg_begin = red_wg;
@@ -256,8 +265,9 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             ea.disc_out = h ? h->disc_dev + (size_t)b * N + n : nullptr;
             ea.flags = h ? h->status_dev + 2 * b : nullptr;
             ea.scratch = bufs[b].scratch;
-            ea.guard = kSplitGramGuard;  // the rank rule flags only under the eps rule
-            ea.split_stats = bufs[b].stats;
+            // the rank rule flags only under the eps rule, and only split Grams
+            ea.guard = f64 ? 0.0 : kSplitGramGuard;
+            ea.split_stats = f64 ? nullptr : bufs[b].stats;
             ea.ncols = (double)v.L * (double)v.B;  // at the capacity shape: an upper bound
             ea.tail_bound = h && h->tail_bound_dev ? h->tail_bound_dev + (size_t)b * N + n
                                                     : nullptr;
@@ -280,7 +290,8 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
                 wg += t.v.nwg;
             }
             sp.grams.push_back({kv.first, (int)kv.second.size(), wg,
-                                put(kv.second.data(), kv.second.size() * sizeof(BatchGramTask))});
+                                put(kv.second.data(), kv.second.size() * sizeof(BatchGramTask)),
+                                f64_class(kv.first)});
         }
         sp.red_off = put(red.data(), red.size() * sizeof(BatchReduceTask));
         sp.red_ntasks = (int)red.size();
@@ -395,19 +406,27 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
     TK_TRY(launch_fill_i32((int*)h->status_dev, 2 * h->B, 0, st));
     for (int s = 0; s < h->N; ++s) {
         const StepPlan& sp = h->steps[s];
-        for (const GramLaunch& g : sp.grams)
-            TK_TRY(launch_gram_bf16s_batched((const BatchGramTask*)(h->tables_dev + g.off),
-                                             g.ntasks, g.total_wg, g.jb, st));
+        bool split = false;
+        for (const GramLaunch& g : sp.grams) {
+            const BatchGramTask* tasks = (const BatchGramTask*)(h->tables_dev + g.off);
+            if (g.f64) {
+                TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 0, st));
+            } else {
+                TK_TRY(launch_gram_bf16s_batched(tasks, g.ntasks, g.total_wg, g.jb, st));
+                split = true;
+            }
+        }
         TK_TRY(launch_gram_reduce_batched((const BatchReduceTask*)(h->tables_dev + sp.red_off),
                                           sp.red_ntasks, sp.red_wg, 0, st));
         TK_TRY(launch_eig_batched((const EigArgs*)(h->tables_dev + sp.eig_off), h->B, sp.jmax,
                                   0, 0, st));
-        if (h->guarded) {
+        if (h->guarded && split) {
             // ranks the split Gram could not certify: FP64 Gram and eigensolver
             // again for those problems (the others' workgroups exit at once)
             for (const GramLaunch& g : sp.grams)
-                TK_TRY(launch_gram_f64_batched((const BatchGramTask*)(h->tables_dev + g.off),
-                                               g.ntasks, g.total_wg, g.jb, 1, st));
+                if (!g.f64)
+                    TK_TRY(launch_gram_f64_batched((const BatchGramTask*)(h->tables_dev + g.off),
+                                                   g.ntasks, g.total_wg, g.jb, 1, st));
             TK_TRY(launch_gram_reduce_batched(
                 (const BatchReduceTask*)(h->tables_dev + sp.red_off), sp.red_ntasks, sp.red_wg,
                 1, st));
