@@ -145,10 +145,11 @@ def slab_check(x64, x32, eps):
     return cpu, out
 
 
-def measured_traffic(name):
-    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy's readings), or None when the kernel's
-    source has changed since the counters were taken."""
+def profiled(name):
+    """The committed profile record of a kernel (profiles/traffic_<name>.json:
+    HBM bytes per launch from FETCH_SIZE and WRITE_SIZE runs, scaled by a
+    plain copy's readings, and the kernel trace's average duration), or None
+    when the kernel's source has changed since it was taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json")) as f:
@@ -157,7 +158,12 @@ def measured_traffic(name):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    return rec["traffic_bytes"] if sha == rec["source_sha256"] else None
+    return rec if sha == rec["source_sha256"] else None
+
+
+def measured_traffic(name):
+    rec = profiled(name)
+    return rec["traffic_bytes"] if rec else None
 
 
 def time_ttm(x, mode, u, precision, reps, stream):
@@ -331,9 +337,12 @@ def config3_leg(x32, w, steps, warmup):
 
 
 def profile_kernels(w, dev, stream):
-    """Launches for hardware-counter runs: 3x the mode-1 split Gram, 3x the
-    mode-1 split TTM (R = 16) and 3x a plain copy of the same FP32 tensor,
-    whose byte counts calibrate the FETCH_SIZE / WRITE_SIZE counters."""
+    """Launches for hardware-counter and trace runs: 3x the mode-1 split Gram
+    and 3x the mode-1 split TTM (R = 16) of combustion128 stored FP32, 3x a
+    plain copy of that tensor (whose byte counts calibrate FETCH_SIZE and
+    WRITE_SIZE), 3x the split Gram of extent 256 (mode 1 of a 256^4 FP32
+    tensor: three pair groups) and 3x the mode-1 FP64 Gram of combustion128
+    stored FP64."""
     x = w.make(dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     res = tucker.sthosvd(x, w.eps, gram_precision="split_bf16", ttm_precision="bf16x3")
@@ -345,8 +354,20 @@ def profile_kernels(w, dev, stream):
         y.copy_(x)
     torch.cuda.synchronize()
     nb = x.numel() * x.element_size()
+    del y
+    x256 = tucker.empty_fortran((256, 256, 256, 256), torch.float32, dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(256)
+    x256.copy_(torch.randn(x256.shape, generator=g, device=dev, dtype=torch.float32))
+    time_gram(x256, 0, "split_bf16", 2, stream)
+    nb256 = x256.numel() * 4
+    del x256
+    torch.cuda.empty_cache()
+    x64 = w.make(dtype=torch.float64, device=dev)
+    time_gram(x64, 0, "fp64", 2, stream)
     log(f"profile-kernels: tensor {nb} bytes; copy reads {nb} and writes {nb} bytes per launch; "
-        f"ttm writes {nb // w.dims[0] * res.ranks[0]} bytes per launch")
+        f"ttm writes {nb // w.dims[0] * res.ranks[0]} bytes per launch; extent-256 Gram reads "
+        f"{nb256} bytes; FP64 Gram reads {x64.numel() * 8} bytes per launch")
 
 
 def batch_leg(dev, steps, warmup, tune=True):
@@ -643,9 +664,12 @@ def main():
         achieved = in_bytes / (k["gram_ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic("gram_split_bf16_combustion128"),
+                "traffic": measured_traffic("gram_split_combustion128"),
                 "kernel": "gram_partial_s16 (mode 1, J=128, FP32 input, int8 matrix cores)",
                 "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": k["gram_ms"]}
+        rec = profiled("gram_split_combustion128")
+        if rec:  # the committed kernel trace's figure, beside this run's HIP events
+            roof["profile_avg_launch_ms"] = rec.get("trace_avg_ms")
     else:
         flops = gram_flops(w.dims[0], x.numel())
         achieved = flops / (k["gram_ms"] / 1e3) / 1e12
