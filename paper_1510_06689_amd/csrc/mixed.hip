@@ -89,36 +89,43 @@ __device__ __forceinline__ unsigned dpp_max(unsigned v) {
 //            each group is two 16-byte loads.
 //   kStrided (otherwise): as kContig, one element per load.
 //   kUnit4   (L == 1, J % 4 == 0, 16-byte aligned; JB >= 128): wave w owns
-//            rows [w JB/8, (w+1) JB/8); lane l holds the four consecutive
-//            rows 4 (l % QPW) of them for the eight columns 8 (l / QPW) + e,
-//            one 16-byte load per column (groups m = the four rows).
-template <int JB, int KT, int MODE, int NBUF = 1>
+//            rows [w JB/NW, (w+1) JB/NW); lane l holds the four consecutive
+//            rows 4 (l % QPW) of them for the eight columns 8 (l / QPW +
+//            s CGW) + e of each of its NSET column sets s, one 16-byte load
+//            per column (groups m = 4 s + the row).
+// NW is the number of waves of the workgroup.
+template <int JB, int KT, int MODE, int NBUF = 1, int NW = kMxWaves>
 struct SplitTile {
+    static constexpr int NT = 64 * NW;                              // threads
     static constexpr int PK = KT + 8;
     static constexpr int NCG = KT / 8;                              // groups per row
-    static constexpr int RW = JB / kMxWaves > 16 ? JB / kMxWaves : 16;  // kUnit rows per wave
+    static constexpr int RW = JB / NW > 16 ? JB / NW : 16;          // kUnit rows per wave
     static constexpr int LPR = 64 / RW;                             // kUnit lanes per row
-    static constexpr int ROWSTEP = kMxThreads / NCG;                // strided rows per pass
-    static constexpr int QPW = JB / kMxWaves / 4;                   // kUnit4 row quads per wave
-    static constexpr int NGRP = MODE == kUnit4  ? 4
+    static constexpr int ROWSTEP = NT / NCG;                        // strided rows per pass
+    static constexpr int QPW = JB / NW / 4;                         // kUnit4 row quads per wave
+    static constexpr int CGW = QPW >= 1 ? 64 / QPW : 1;             // kUnit4 column groups per set
+    static constexpr int NSET = MODE == kUnit4 ? KT / (8 * CGW) : 1;  // kUnit4 sets per lane
+    static constexpr int NGRP = MODE == kUnit4  ? 4 * NSET
                                 : MODE == kUnit ? NCG / LPR
-                                                : JB * NCG / kMxThreads;
+                                                : JB * NCG / NT;
     static_assert(RW <= 64 && NCG % LPR == 0, "unit mapping");
     static_assert(MODE == kUnit || MODE == kUnit4 ||
-                      (NGRP >= 1 && JB * NCG % kMxThreads == 0 && NCG <= 16),
+                      (NGRP >= 1 && JB * NCG % NT == 0 && NCG <= 16),
                   "strided mapping");
-    static_assert(MODE != kUnit4 || (QPW >= 1 && 64 % QPW == 0 && KT == 8 * (64 / QPW)),
+    static_assert(MODE != kUnit4 ||
+                      (QPW >= 1 && 64 % QPW == 0 && NSET >= 1 && KT == 8 * CGW * NSET &&
+                       NSET * 8 <= 32),
                   "kUnit4 mapping: the wave's lanes cover its rows and the tile's columns");
 
     float vb[NBUF][NGRP][8];  // NBUF register tiles (loads of one in flight while another is split)
-    unsigned okm[NBUF];       // kUnit4: bit e set if column group element e is inside the tile
+    unsigned okm[NBUF];       // kUnit4: bit 8 s + e set if set s, element e is inside the tile
     int i0, cg0;
     bool owner;      // kUnit: this wave holds rows
     int coff[8];     // strided: offsets of the thread's 8 columns inside a tile
     // Representation error of the split: per row of the thread, the sum of
     // d^2 over its elements, d = x - 2^(E-7) (hi + lo) exactly, and the
     // largest row exponent E it used.
-    static constexpr int NROW = MODE == kUnit ? 1 : NGRP;
+    static constexpr int NROW = MODE == kUnit ? 1 : MODE == kUnit4 ? 4 : NGRP;
     double rd[NROW];
     int emax;
 
@@ -134,7 +141,7 @@ struct SplitTile {
         if (MODE == kUnit4) {
             const int w = tid >> 6, l = tid & 63;
             owner = true;
-            i0 = w * (JB / kMxWaves) + 4 * (l % QPW);
+            i0 = w * (JB / NW) + 4 * (l % QPW);
             cg0 = l / QPW;
         } else if (MODE == kUnit) {
             const int w = tid >> 6, l = tid & 63;
@@ -150,10 +157,10 @@ struct SplitTile {
         }
     }
     __device__ __forceinline__ int row_of(int m) const {
-        return MODE == kUnit ? i0 : MODE == kUnit4 ? i0 + m : i0 + m * ROWSTEP;
+        return MODE == kUnit ? i0 : MODE == kUnit4 ? i0 + (m & 3) : i0 + m * ROWSTEP;
     }
     __device__ __forceinline__ int cg_of(int m) const {
-        return MODE == kUnit ? cg0 + m * LPR : cg0;
+        return MODE == kUnit ? cg0 + m * LPR : MODE == kUnit4 ? cg0 + CGW * (m >> 2) : cg0;
     }
 
     // kUnit4, full tile t with J == JB (L == 1: the tile is the KT JB floats
@@ -166,18 +173,20 @@ struct SplitTile {
     __device__ __forceinline__ void load_full(const float* __restrict__ y, int64_t t) {
         static_assert(MODE == kUnit4, "full-tile loads: kUnit4 only");
         float(&v)[NGRP][8] = vb[B];
-        okm[B] = 0xffu;
+        okm[B] = (1u << (8 * NSET)) - 1u;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)uni(y + t * (int64_t)(KT * JB)), (short)0, KT * JB * (int)sizeof(float),
             0x00020000);  // gfx9 word 3: 32-bit data format, untyped access
         const int voff = (8 * cg0 * JB + i0) * (int)sizeof(float);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const f4_t x = __builtin_amdgcn_raw_buffer_load_b128(
-                rs, voff, e * JB * (int)sizeof(float), 0);
+        for (int st = 0; st < NSET; ++st)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j][e] = x[j];
-        }
+            for (int e = 0; e < 8; ++e) {
+                const f4_t x = __builtin_amdgcn_raw_buffer_load_b128(
+                    rs, voff, (8 * CGW * st + e) * JB * (int)sizeof(float), 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[4 * st + j][e] = x[j];
+            }
     }
 
     template <int B = 0>
@@ -190,27 +199,32 @@ struct SplitTile {
             // Elements outside the tile come from clamped addresses and are
             // zeroed when the tile is split, so no load result is used here.
             if (t.ncols == KT && J == JB) {
-                okm[B] = 0xffu;
+                okm[B] = (1u << (8 * NSET)) - 1u;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const f4_t x = *(const f4_t*)(y + t.base + (int64_t)(8 * cg0 + e) * JB + i0);
+                for (int st = 0; st < NSET; ++st)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j][e] = x[j];
-                }
+                    for (int e = 0; e < 8; ++e) {
+                        const f4_t x = *(const f4_t*)(y + t.base +
+                                                      (int64_t)(8 * (cg0 + CGW * st) + e) * JB + i0);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v[4 * st + j][e] = x[j];
+                    }
             } else {
                 // J % 4 == 0: a row quad is wholly in or out
                 const bool rok = i0 < J;
                 const int ic = rok ? i0 : J - 4;
                 unsigned mk = 0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int kk = 8 * cg0 + e;
-                    mk |= (rok && kk < t.ncols) ? 1u << e : 0u;
-                    const int kc = kk < t.ncols ? kk : t.ncols - 1;
-                    const f4_t x = *(const f4_t*)(y + t.base + (int64_t)kc * J + ic);
+                for (int st = 0; st < NSET; ++st)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j][e] = x[j];
-                }
+                    for (int e = 0; e < 8; ++e) {
+                        const int kk = 8 * (cg0 + CGW * st) + e;
+                        mk |= (rok && kk < t.ncols) ? 1u << (8 * st + e) : 0u;
+                        const int kc = kk < t.ncols ? kk : t.ncols - 1;
+                        const f4_t x = *(const f4_t*)(y + t.base + (int64_t)kc * J + ic);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v[4 * st + j][e] = x[j];
+                    }
                 okm[B] = mk;
             }
         } else if (MODE == kUnit) {
@@ -258,12 +272,16 @@ struct SplitTile {
         unsigned b = 0;
         if (MODE == kUnit4) {
             // |x| maxima as floats (abs is a free operand modifier); NaN and
-            // Inf still reach the Gram through d = x 2^(15-E) - q
-            float f = __builtin_fmaxf(__builtin_fabsf(v[m][0]), __builtin_fabsf(v[m][1]));
+            // Inf still reach the Gram through d = x 2^(15-E) - q.  Row m & 3
+            // over all of the lane's column sets.
+            const int j = m & 3;
+            float f = __builtin_fmaxf(__builtin_fabsf(v[j][0]), __builtin_fabsf(v[j][1]));
 #pragma unroll
-            for (int e = 2; e < 8; e += 2)
-                f = __builtin_fmaxf(f, __builtin_fmaxf(__builtin_fabsf(v[m][e]),
-                                                       __builtin_fabsf(v[m][e + 1])));
+            for (int st = 0; st < NSET; ++st)
+#pragma unroll
+                for (int e = st == 0 ? 2 : 0; e < 8; e += 2)
+                    f = __builtin_fmaxf(f, __builtin_fmaxf(__builtin_fabsf(v[4 * st + j][e]),
+                                                           __builtin_fabsf(v[4 * st + j][e + 1])));
             if constexpr (QPW <= 4) f = lane_fmax<4>(f);
             if constexpr (QPW <= 8) f = lane_fmax<8>(f);
             if constexpr (QPW <= 16) f = lane_fmax<16>(f);
@@ -364,13 +382,15 @@ struct SplitTile {
     __device__ __forceinline__ void store16(unsigned char* hi, unsigned char* lo, double* sc,
                                             bool count = true) {
         float(&v)[NGRP][8] = vb[B];
-        if (MODE == kUnit4 && okm[B] != 0xffu) {  // a partial tile: zero what lies outside
+        if (MODE == kUnit4 && okm[B] != (1u << (8 * NSET)) - 1u) {  // a partial tile:
+#pragma unroll                                                     // zero what lies outside
+            for (int st = 0; st < NSET; ++st)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const bool ok = (okm[B] >> e) & 1u;
+                for (int e = 0; e < 8; ++e) {
+                    const bool ok = (okm[B] >> (8 * st + e)) & 1u;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[j][e] = ok ? v[j][e] : 0.f;
-            }
+                    for (int j = 0; j < 4; ++j) v[4 * st + j][e] = ok ? v[4 * st + j][e] : 0.f;
+                }
         }
         constexpr int PKB = KT + 16;
         constexpr float kMagic = 12583040.0f;  // 1.5 2^23 + 128
@@ -378,9 +398,10 @@ struct SplitTile {
         if (MODE == kUnit) mb = row_max_bits<B>(0);
         float rs = 0.f;
         int sh = 0;
+        int shr[4] = {0, 0, 0, 0};  // kUnit4: the row's shift, from its first set
 #pragma unroll
         for (int m = 0; m < NGRP; ++m) {
-            if (MODE != kUnit || m == 0) {
+            if (MODE == kUnit4 ? m < 4 : (MODE != kUnit || m == 0)) {
                 if (MODE != kUnit) mb = row_max_bits<B>(m);
                 // E: the exponent of max |x| (1 + 2^-8) rounded up, so that
                 // max |x| 2^(15-E) < 32768 / 1.004 < 32639.5; zero rows get
@@ -388,6 +409,9 @@ struct SplitTile {
                 const unsigned bb = __float_as_uint(__uint_as_float(mb) * 1.004f);
                 const int E = (int)(bb >> 23) - 126;
                 sh = 15 - (E < -125 ? -125 : E);
+                if (MODE == kUnit4) shr[m & 3] = sh;
+            } else if (MODE == kUnit4) {
+                sh = shr[m & 3];
             }
             unsigned b[8];
             float gs = 0.f;
@@ -420,7 +444,7 @@ struct SplitTile {
             if (MODE == kUnit) {
                 rs += gs;
             } else if (r < JB && count) {
-                rd[m] += __builtin_ldexp((double)gs, -2 * sh);
+                rd[MODE == kUnit4 ? (m & 3) : m] += __builtin_ldexp((double)gs, -2 * sh);
                 emax = max(emax, 15 - sh);
             }
         }
@@ -686,11 +710,11 @@ constexpr size_t s16_buf_bytes() {
 // the matrix cores and tile t + 1 is split, so every load has about two
 // iterations to arrive.  Its loads are unconditional (past the range end the
 // last tile is loaded again and split without counting its statistics).
-template <int JB, int KT, int NPW, int MODE, int NBUF = 1>
+template <int JB, int KT, int NPW, int MODE, int NBUF = 1, int NW = kMxWaves>
 __device__ __forceinline__ void gram_s16_body(
     const float* __restrict__ y, const TileMap& tm, int npairs16, int pairs_per_group, int group,
     int64_t t0, int64_t t1, double* __restrict__ out, double* aux, double* lds_raw) {
-    using Ld = SplitTile<JB, KT, MODE, NBUF>;
+    using Ld = SplitTile<JB, KT, MODE, NBUF, NW>;
     constexpr int PKB = KT + 16;
     constexpr int PLANE = JB * PKB;
     constexpr size_t BUF = s16_buf_bytes<JB, KT>();
@@ -703,7 +727,7 @@ __device__ __forceinline__ void gram_s16_body(
     const int r16 = lane & 15, kq = lane >> 4;
     const int g0 = group * pairs_per_group;
 
-    constexpr bool kSched = JB == 128;  // the fixed per-wave schedule above
+    constexpr bool kSched = JB == 128 && NW == 8;  // the fixed per-wave schedule above
     static_assert(!kSched || NPW == 5, "the extent-128 schedule has up to 5 pairs per wave");
     int bi[NPW], bj[NPW], aoff[NPW], boff[NPW];
     bool act[NPW];
@@ -715,7 +739,7 @@ __device__ __forceinline__ void gram_s16_body(
             bi[q] = ws.blk[ws.pa[q]];
             bj[q] = ws.blk[ws.pb[q]];
         } else {
-            const int pl = q * kMxWaves + ((q & 1) ? kMxWaves - 1 - wave : wave);
+            const int pl = q * NW + ((q & 1) ? NW - 1 - wave : wave);
             const int p = g0 + pl;
             act[q] = pl < pairs_per_group && p < npairs16;
             pair32_of(act[q] ? p : 0, NB, bi[q], bj[q]);  // the upper-triangle order, NB blocks
@@ -876,7 +900,7 @@ __device__ __forceinline__ void gram_s16_body(
 
     // subtract each row's sum of d^2 from its diagonal entry (as the bf16 body)
     double* rowd = lds_raw + 64;
-    for (int i = tid; i < JB; i += kMxThreads) rowd[i] = 0.0;
+    for (int i = tid; i < JB; i += 64 * NW) rowd[i] = 0.0;
     __syncthreads();
     ld.row_sums(rowd, lane);
     __syncthreads();
@@ -895,8 +919,8 @@ __device__ __forceinline__ void gram_s16_body(
     if (aux) split_stats_out(ld.total(), ld.emax, aux, lds_raw);  // uniform branch
 }
 
-template <int JB, int KT, int NPW, int MODE, int NBUF>
-__global__ __launch_bounds__(kMxThreads) void gram_partial_s16(
+template <int JB, int KT, int NPW, int MODE, int NBUF, int NW>
+__global__ __launch_bounds__(64 * NW) void gram_partial_s16(
     const float* __restrict__ y, TileMap tm, int npairs16, int pairs_per_group, int P, int G,
     double* __restrict__ partial) {
     extern __shared__ double lds_raw[];
@@ -905,7 +929,7 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_s16(
     const int64_t t0 = tm.ntiles * (int64_t)p / P;
     const int64_t t1 = tm.ntiles * (int64_t)(p + 1) / P;
     double* aux = g == 0 ? partial + (int64_t)P * npairs16 * 256 + 2 * p : nullptr;
-    gram_s16_body<JB, KT, NPW, MODE, NBUF>(y, tm, npairs16, pairs_per_group, g, t0, t1,
+    gram_s16_body<JB, KT, NPW, MODE, NBUF, NW>(y, tm, npairs16, pairs_per_group, g, t0, t1,
                                            partial + (int64_t)p * npairs16 * 256, aux, lds_raw);
 }
 
@@ -929,19 +953,25 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
 // (each re-reads the tensor), workgroups per CU.  Extents up to 256 run the
 // int8 kernel on 16-block pairs, 512 the bf16 kernel on 32-block pairs.
 struct MxGramShape {
-    int KT, NPW, G, per_cu;
+    int KT, NPW, G, per_cu, NW;  // NW: waves per workgroup
 };
 template <int JB>
 constexpr bool mx_int8() {
     return JB <= 256;
 }
-template <int JB>
+// UNIT: the view has L == 1.  At extent 256 its loaders leave room for 9
+// pairs per wave (two pair groups of 68: every tile split twice), the
+// strided loaders for 6 (three groups of 46).  A pair's int32 sums live only
+// from its first MFMA to its flush; the FP64 accumulators of all the wave's
+// pairs (8 registers each) are what limits the count.
+template <int JB, bool UNIT = false>
 constexpr MxGramShape mx_gram_shape() {
-    return JB == 32    ? MxGramShape{128, 1, 1, 2}   //   3 16-pairs
-           : JB == 64  ? MxGramShape{128, 2, 1, 2}   //  10 16-pairs
-           : JB == 128 ? MxGramShape{128, 5, 1, 1}   //  36 16-pairs, 9 per SIMD
-           : JB == 256 ? MxGramShape{64, 6, 3, 1}    // 136 16-pairs: 3 groups of 46
-                       : MxGramShape{16, 2, 9, 1};   // 136 32-pairs: 9 groups of 16
+    return JB == 32    ? MxGramShape{128, 1, 1, 2, 8}    //   3 16-pairs
+           : JB == 64  ? MxGramShape{128, 2, 1, 2, 8}    //  10 16-pairs
+           : JB == 128 ? MxGramShape{128, 5, 1, 1, 8}    //  36 16-pairs, 9 per SIMD
+           : JB == 256 ? (UNIT ? MxGramShape{64, 9, 2, 1, 8}     // 136 16-pairs: 2 x 68
+                               : MxGramShape{64, 6, 3, 1, 8})    //               3 x 46
+                       : MxGramShape{16, 2, 9, 1, 8};    // 136 32-pairs: 9 groups of 16
 }
 template <int JB>
 constexpr int mx_owned_pairs() {  // pairs the kernel's owner waves are dealt
@@ -954,11 +984,11 @@ static int mx_round_jb(int J) {
     return jb;
 }
 
-template <int JB>
+template <int JB, bool UNIT>
 static GramPlan mx_plan(const ModeView& v) {
-    constexpr MxGramShape gs = mx_gram_shape<JB>();
+    constexpr MxGramShape gs = mx_gram_shape<JB, UNIT>();
     constexpr int owned = mx_owned_pairs<JB>();
-    static_assert(kMxWaves * gs.NPW >= (owned + gs.G - 1) / gs.G,
+    static_assert(gs.NW * gs.NPW >= (owned + gs.G - 1) / gs.G,
                   "every pair of a group needs an owner wave");
     GramPlan pl{};
     TileMap tm = make_tiles(v, gs.KT);
@@ -977,24 +1007,25 @@ static GramPlan mx_plan(const ModeView& v) {
 
 GramPlan plan_gram_mixed(const ModeView& v) {
     switch (mx_round_jb(v.J)) {
-        case 32: return mx_plan<32>(v);
-        case 64: return mx_plan<64>(v);
-        case 128: return mx_plan<128>(v);
-        case 256: return mx_plan<256>(v);
-        default: return mx_plan<512>(v);
+        case 32: return mx_plan<32, false>(v);
+        case 64: return mx_plan<64, false>(v);
+        case 128: return mx_plan<128, false>(v);
+        case 256: return v.L == 1 ? mx_plan<256, true>(v) : mx_plan<256, false>(v);
+        default: return mx_plan<512, false>(v);
     }
 }
 
 template <int JB, int MODE, int NBUF = 1>
 static int mx_launch(const float* y, const TileMap& tm, const GramPlan& pl, double* partial,
                      hipStream_t st) {
-    constexpr MxGramShape gs = mx_gram_shape<JB>();
+    // the shape the plan chose (L == 1 exactly for the unit loaders)
+    constexpr MxGramShape gs = mx_gram_shape<JB, MODE == kUnit || MODE == kUnit4>();
     if constexpr (mx_int8<JB>()) {
-        auto fn = gram_partial_s16<JB, gs.KT, gs.NPW, MODE, NBUF>;
+        auto fn = gram_partial_s16<JB, gs.KT, gs.NPW, MODE, NBUF, gs.NW>;
         const size_t lds = 2 * s16_buf_bytes<JB, gs.KT>();
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-        hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(kMxThreads), lds, st, y, tm, pl.npairs,
+        hipLaunchKernelGGL(fn, dim3(pl.P * pl.G), dim3(64 * gs.NW), lds, st, y, tm, pl.npairs,
                            pl.pairs_per_group, pl.P, pl.G, partial);
     } else {
         auto fn = gram_partial_bf16s<JB, gs.KT, gs.NPW, MODE>;
@@ -1016,6 +1047,7 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
     TileMap tm = make_tiles(v, pl.KT);
     if constexpr (JB == 128 || JB == 256) {
         if (v.L == 1 && v.J % 4 == 0 && ((uintptr_t)y & 15) == 0)
+            // two register tiles (J == JB only)
             return v.J == JB ? mx_launch<JB, kUnit4, 2>(y, tm, pl, partial, st)
                              : mx_launch<JB, kUnit4, 1>(y, tm, pl, partial, st);
     }
