@@ -412,7 +412,7 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
             if (g.f64) {
                 TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 0, st));
             } else {
-                TK_TRY(launch_gram_bf16s_batched(tasks, g.ntasks, g.total_wg, g.jb, st));
+                TK_TRY(launch_gram_split_batched(tasks, g.ntasks, g.total_wg, g.jb, st));
                 split = true;
             }
         }

@@ -1068,7 +1068,7 @@ __device__ __forceinline__ int batch_loader(const ModeView& mv, const float* y) 
 }
 
 template <int JB, int MODE>
-__global__ __launch_bounds__(kMxThreads) void gram_bf16s_batched(
+__global__ __launch_bounds__(kMxThreads) void gram_s16_batched(
     const BatchGramTask* __restrict__ tasks, int ntasks) {
     extern __shared__ double lds_raw[];
     constexpr MxGramShape gs = mx_gram_shape<JB>();
@@ -1107,12 +1107,12 @@ int mx_gram_kt(int jb) {
 }
 
 template <int JB>
-static int launch_bf16s_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
+static int launch_split_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
                                   hipStream_t st) {
     static_assert(mx_gram_shape<JB>().G == 1, "batches need a single pair group");
     const size_t lds = 2 * s16_buf_bytes<JB, mx_gram_shape<JB>().KT>();
-    for (const auto fn : {gram_bf16s_batched<JB, kUnit>, gram_bf16s_batched<JB, kContig>,
-                          gram_bf16s_batched<JB, kStrided>}) {
+    for (const auto fn : {gram_s16_batched<JB, kUnit>, gram_s16_batched<JB, kContig>,
+                          gram_s16_batched<JB, kStrided>}) {
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
         hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kMxThreads), lds, st, tasks, ntasks);
@@ -1121,12 +1121,12 @@ static int launch_bf16s_batched_t(const BatchGramTask* tasks, int ntasks, int to
     return TK_OK;
 }
 
-int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
                               hipStream_t st) {
     switch (jb) {
-        case 32: return launch_bf16s_batched_t<32>(tasks_dev, ntasks, total_wg, st);
-        case 64: return launch_bf16s_batched_t<64>(tasks_dev, ntasks, total_wg, st);
-        case 128: return launch_bf16s_batched_t<128>(tasks_dev, ntasks, total_wg, st);
+        case 32: return launch_split_batched_t<32>(tasks_dev, ntasks, total_wg, st);
+        case 64: return launch_split_batched_t<64>(tasks_dev, ntasks, total_wg, st);
+        case 128: return launch_split_batched_t<128>(tasks_dev, ntasks, total_wg, st);
         default: return fail(TK_ERR_UNSUPPORTED, "batched split Gram: extent class %d", jb);
     }
 }

@@ -399,7 +399,7 @@ struct BatchReduceTask {
     const int* nparts;
 };
 
-int launch_gram_bf16s_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
+int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
                               hipStream_t st);
 int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
                             int kmax, int precision, hipStream_t st);
