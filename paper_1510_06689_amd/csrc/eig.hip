@@ -31,6 +31,7 @@
 // J = 64 on step 2 runs in a launch of its own (eig_multisect, one wave per
 // eigenvalue) between two launches of the solver; no host sync.
 #include <cfloat>
+#include <type_traits>
 
 #include "tk_common.hpp"
 
@@ -52,6 +53,15 @@ __device__ __forceinline__ double dpp_move(double v) {
     lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
     hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E - 1 in order.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 __device__ __forceinline__ double read_lane(double v, int lane) {
@@ -200,104 +210,124 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
     }
     double* Hs = reg;
     constexpr int NS = (JP + 63) / 64;  // per-lane slots of a wave-wide reduction
-    // Straight-line code below: every load stays inside four JP-long vector
-    // buffers (zeroed first, so stale entries are finite; they sit in the
-    // 1024-double area after misc, which only the global-A path uses), and
-    // inactive terms are removed by exact 0/1 factors rather than by branches.
-    static_assert(4 * JP <= kEigThreads, "vector buffers must fit the partial-sum area");
+    // Every load below stays inside the reflector store (zeroed first, so
+    // that entries no step writes are exact zeros: reflector k is written
+    // from column k + 1 on) and four JP-long vector buffers in the
+    // 1024-double area after misc (zeroed too; the global-A path alone uses
+    // it otherwise).  A's diagonal and superdiagonal are kept beside the
+    // registers in LDS (dg, sd), updated by lane 0 of each row with the same
+    // formula as the registers, so that the pivot's a_kk and a_k,k+1 are an
+    // LDS read rather than a register chosen by a run-time index.  Finished
+    // rows and columns see v = p = 0, so the register loops need no masks.
+    static_assert(6 * JP <= kEigThreads, "vector buffers must fit the partial-sum area");
     double* vbuf = red + 64 + 8;
+    double* dg = vbuf + 4 * JP;
+    double* sd = dg + JP;
     for (int i = tid; i < 4 * JP; i += kEigThreads) vbuf[i] = 0.0;
+    for (int i = tid; i < JP; i += kEigThreads) {
+        dg[i] = i < Jr ? src[i + (size_t)ld * i] : 0.0;
+        sd[i] = i + 1 < Jr ? src[i + (size_t)ld * (i + 1)] : 0.0;
+    }
+    for (int i = tid; i < (Jr > 2 ? Jr - 2 : 0) * JP; i += kEigThreads) Hs[i] = 0.0;
     __syncthreads();
-    for (int k = 0; k + 2 < Jr; ++k) {
-        double* vs = Hs + (size_t)k * JP;        // v = reflector k: v_{k+1} = 1, zero outside k < j < Jr
-        double* ps = vbuf + (2 + (k & 1)) * JP;  // p = tau A22 v, zero outside k < i < Jr
-        double* sg = red + 40 + (k & 1);         // tau of column k
-        if (ri == k) {
-            // The owners of row k (= column k, x = its part beyond the diagonal)
-            // form the reflector alone, in the form of LAPACK's dlarfg:
-            // alpha = -sign(x_0) |x|, tau = 1 + |x_0| / |x|, v = x / (x_0 - alpha)
-            // (one reciprocal square root and one reciprocal), and publish v.
-            double sq[4] = {0.0, 0.0, 0.0, 0.0};
+    // Columns run in blocks of eight, the block index KB a compile-time
+    // constant: chunks below KB are finished for every column of the block
+    // (their v and p are zero), so each loop starts at chunk KB with no test,
+    // and only chunks KB and KB + 1 can hold the pivot column k + 1.
+    static_for<0, NQ>([&](auto kbc) {
+        constexpr int KB = decltype(kbc)::value;
+        const int kend = min(8 * KB + 8, Jr - 2);
+        for (int k = 8 * KB; k < kend; ++k) {
+            double* vs = Hs + (size_t)k * JP;        // v = reflector k: v_{k+1} = 1, zero outside k < j < Jr
+            double* ps = vbuf + (2 + (k & 1)) * JP;  // p = tau A22 v, zero outside k < i < Jr
+            double* sg = red + 40 + (k & 1);         // tau of column k
+            // The row index goes through an empty asm so that the compiler
+            // cannot use ri == k to replace the uniform k by the per-lane ri
+            // inside the owner branch (that turns every column test below
+            // into a per-lane mask held across the loop).
+            int ri_k = ri;
+            asm volatile("" : "+v"(ri_k));
+            if (ri_k == k) {
+                // The owners of row k (= column k, x = its part beyond the
+                // diagonal) form the reflector alone, in the form of LAPACK's
+                // dlarfg: alpha = -sign(x_0) |x|, tau = 1 + |x_0| / |x|,
+                // v = x / (x_0 - alpha) (one reciprocal square root and one
+                // reciprocal), and publish v.
+                double sq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int j = rc + 8 * q;
-                sq[q & 3] = fma(((j >= k + 2 && j < Jr) ? 1.0 : 0.0) * av[q], av[q], sq[q & 3]);
-            }
-            const double sigma = row8_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
-            // a_{k,k+1} and a_kk: register (k + 1) / 8 (resp. k / 8) of the
-            // owner lane of their column; both indices are uniform
-            const int lane0 = 8 * (k & 7);
-            const double x0 = read_lane(av[(k + 1) >> 3], lane0 + ((k + 1) & 7));
-            const double akk = read_lane(av[k >> 3], lane0 + (k & 7));
-            double tau = 0.0, alpha = x0, inv_v0 = 0.0;
-            if (sigma != 0.0) {
-                const double ss = fma(x0, x0, sigma);
-                const double r = rsq(ss);  // 1 / |x|
-                const double mu = ss * r;
-                const double sgn = x0 < 0.0 ? -1.0 : 1.0;
-                alpha = -sgn * mu;
-                tau = fma(fabs(x0), r, 1.0);
-                inv_v0 = sgn * recip(fabs(x0) + mu);
-            }
+                for (int q = KB; q < NQ; ++q) {
+                    const double m = (q > KB + 1 || rc + 8 * q >= k + 2) ? av[q] : 0.0;
+                    sq[q & 3] = fma(m, m, sq[q & 3]);
+                }
+                const double sigma = row8_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
+                const double x0 = sd[k], akk = dg[k];
+                double tau = 0.0, alpha = x0, inv_v0 = 0.0;
+                if (sigma != 0.0) {
+                    const double ss = fma(x0, x0, sigma);
+                    const double r = rsq(ss);  // 1 / |x|
+                    const double mu = ss * r;
+                    const double sgn = x0 < 0.0 ? -1.0 : 1.0;
+                    alpha = -sgn * mu;
+                    tau = fma(fabs(x0), r, 1.0);
+                    inv_v0 = sgn * recip(fabs(x0) + mu);
+                }
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int j = rc + 8 * q;
-                vs[j] = j == k + 1 ? 1.0 : ((j > k + 1 && j < Jr) ? av[q] * inv_v0 : 0.0);
-            }
-            if (rc == 0) {
-                *sg = tau;
-                d[koff + k] = akk;
-                e[koff + k] = alpha;
-                beta[koff + k] = tau;
-            }
-        }
-        __syncthreads();
-        const double tau = *sg;
-        if (tau == 0.0) continue;  // uniform: the reflector is the identity
-        // Rows and columns <= k are finished: a wave whose 8 rows are all <= k
-        // has nothing to form or update, nor has column group q (columns
-        // 8q .. 8q + 7) once 8q + 7 <= k.  Both tests are uniform over a wave.
-        const bool wact = 8 * wave + 7 > k;
-        double vq[NQ];
-        double part = 0.0;
-        if (wact) {
-            double pr[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                vq[q] = 0.0;
-                if (8 * q + 7 > k) {
-                    vq[q] = vs[rc + 8 * q];
-                    pr[q & 3] = fma(av[q], vq[q], pr[q & 3]);
+                for (int q = KB; q < NQ; ++q) {
+                    const int j = rc + 8 * q;
+                    const double vj = av[q] * inv_v0;  // av is 0 beyond Jr
+                    vs[j] = q > KB + 1 ? vj : (j == k + 1 ? 1.0 : (j > k + 1 ? vj : 0.0));
+                }
+                if (rc == 0) {
+                    *sg = tau;
+                    d[koff + k] = akk;
+                    e[koff + k] = alpha;
+                    beta[koff + k] = tau;
                 }
             }
-            part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
-        }
-        if (rc == 0 && ri < JP) ps[ri] = (wact && ri > k && rowok) ? tau * part : 0.0;
-        __syncthreads();
-        if (!wact) continue;  // uniform over the wave; it still meets every barrier
-        // A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v.  Every wave forms
-        // p.v with the same bits, and w_i, w_j come from the same formula on
-        // the same values, so A stays exactly symmetric; entries outside the
-        // trailing block see v = w = 0.
-        double pv = 0.0;
+            __syncthreads();
+            const double tau = *sg;
+            if (tau == 0.0) continue;  // uniform: the reflector is the identity
+            // A wave whose 8 rows are all <= k has nothing to form or update (uniform).
+            const bool wact = 8 * wave + 7 > k;
+            double part = 0.0;
+            if (wact) {
+                double pr[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int r = 0; r < NS; ++r) {
-            const int j = lane + 64 * r;
-            if (j < JP) pv = fma(ps[j], vs[j], pv);
-        }
-        const double half = 0.5 * tau * wave_sum(pv);
-        const int ric = ri < JP ? ri : 0;
-        const double vi = vs[ric], wi = fma(-half, vi, ps[ric]);
+                for (int q = KB; q < NQ; ++q) pr[q & 3] = fma(av[q], vs[rc + 8 * q], pr[q & 3]);
+                part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
+            }
+            if (rc == 0 && ri < JP) ps[ri] = (wact && ri > k && rowok) ? tau * part : 0.0;
+            __syncthreads();
+            if (!wact) continue;  // uniform over the wave; it still meets every barrier
+            // A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v.  Every wave
+            // forms p.v with the same bits, and w_i, w_j come from the same
+            // formula on the same values, so A stays exactly symmetric;
+            // entries outside the trailing block see v = w = 0.
+            double pv = 0.0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (8 * q + 7 > k) {
-                const int j = rc + 8 * q;
-                const double vj = vq[q];
-                const double wj = fma(-half, vj, ps[j]);
+            for (int r = 0; r < NS; ++r) {
+                const int j = lane + 64 * r;
+                if (j < JP) pv = fma(ps[j], vs[j], pv);
+            }
+            const double half = 0.5 * tau * wave_sum(pv);
+            const int ric = ri < JP ? ri : 0;
+            const double vi = vs[ric], wi = fma(-half, vi, ps[ric]);
+#pragma unroll
+            for (int q = KB; q < NQ; ++q) {
+                const double vj = vs[rc + 8 * q];
+                const double wj = fma(-half, vj, ps[rc + 8 * q]);
                 av[q] -= __dadd_rn(__dmul_rn(vi, wj), __dmul_rn(wi, vj));
             }
+            // the same update of a_ii and a_i,i+1 beside the registers
+            if (rc == 0 && ri > k && rowok) {
+                dg[ri] -= __dadd_rn(__dmul_rn(vi, wi), __dmul_rn(wi, vi));
+                if (ri + 1 < Jr) {
+                    const double v1 = vs[ri + 1], w1 = fma(-half, v1, ps[ri + 1]);
+                    sd[ri] -= __dadd_rn(__dmul_rn(vi, w1), __dmul_rn(wi, v1));
+                }
+            }
         }
-    }
+    });
     // the trailing 2 x 2 block (or 1 x 1)
     if (ri >= Jr - 2 && rowok) {
 #pragma unroll
