@@ -43,6 +43,12 @@ constexpr int kInvIters = 2;
 constexpr int kPanel = 8;  // columns per panel of the global-memory reduction
 constexpr int kLuArrays = 6;  // u0 (reciprocal), u1, u2, multiplier, pivot flag, x
 constexpr int kMaxVecSlots = TK_MAX_MODE_DIM / 64;  // per-lane elements of one vector
+constexpr int kSweepRows = 4;  // rows per block of the inverse-iteration sweeps
+
+// Rows of the inverse-iteration arrays: J padded to whole sweep blocks.
+__host__ __device__ constexpr int eig_sweep_rows(int J) {
+    return (J + kSweepRows - 1) / kSweepRows * kSweepRows;
+}
 
 // Moves a double across lanes with one DPP pattern (applied to both 32-bit
 // halves); lanes the pattern does not write receive 0.
@@ -127,7 +133,9 @@ static size_t eig_region_doubles(int J) {
     const size_t lds_doubles = 160 * 1024 / sizeof(double);
     size_t cap = lds_doubles - eig_small_doubles(J) - 128;
     if (cap > 16384) cap = 16384;                 // J <= 128 also holds A here (J*J <= 16384)
-    const size_t want = (size_t)kLuArrays * J * J;  // room for every vector in one batch
+    // room for every vector in one batch: a record of kLuArrays values per
+    // padded row plus one, and two scale factors, per vector
+    const size_t want = ((size_t)kLuArrays * eig_sweep_rows(J) + 3) * J;
     return want < cap ? want : cap;
 }
 
@@ -178,6 +186,13 @@ __device__ __forceinline__ double row8_sum(double v) {
     v += dpp_move<0xb1, 0xf, false>(v);   // quad_perm [1,0,3,2]
     v += dpp_move<0x4e, 0xf, false>(v);   // quad_perm [2,3,0,1]
     v += dpp_move<0x141, 0xf, false>(v);  // row_half_mirror
+    return v;
+}
+
+// Sum over the 16 lanes of a row (every lane gets the same bits).
+__device__ __forceinline__ double row16_sum(double v) {
+    v = row8_sum(v);
+    v += dpp_move<0x140, 0xf, false>(v);  // row_mirror
     return v;
 }
 
@@ -387,6 +402,18 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     double* X = a.u;                          // column-major J x R
     double* ho = eig_handoff(a.scratch, J);   // hand-off between split launches
     double sc, tnorm;
+    // the rank rule's global inputs, loaded now so that their latency
+    // overlaps the earlier phases
+    double nu_in = 0.0, stat_d2 = 0.0, stat_e = 0.0;
+    if constexpr (PH != 1) {
+        if (tid == 0) {
+            if (a.fixed_rank <= 0) nu_in = *a.nu;
+            if (a.guard > 0.0 && a.split_stats) {
+                stat_d2 = a.split_stats[0];
+                stat_e = a.split_stats[1];
+            }
+        }
+    }
 
     if constexpr (PH != 3) {
     if constexpr (JP > 0) {
@@ -660,22 +687,45 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         const double l = raw ? lam[r] : fmax(lam[r], 0.0);
         return a.aug ? l * l : l;
     };
-    for (int i = tid; i < Jv; i += kEigThreads) a.lambda[i] = a.aug ? val(i) : lam[i];
+    // the values of the tail sums, formed in parallel (pw is free after step 1)
+    double* vals = pw;
+    for (int i = tid; i < Jv; i += kEigThreads) {
+        const double v = val(i);
+        vals[i] = v;
+        a.lambda[i] = a.aug ? v : lam[i];
+    }
+    __syncthreads();
 
     // ---- 3. rank rule ---------------------------------------------------
     if (tid == 0) {
         int R;
         double tail = 0.0;
         const bool eps_rule = a.fixed_rank <= 0;
-        const double tau = eps_rule ? a.eps2_over_n * (*a.nu) : 0.0;
+        const double tau = eps_rule ? a.eps2_over_n * nu_in : 0.0;
         if (!eps_rule) {
             R = a.fixed_rank < Jv ? a.fixed_rank : Jv;
-            for (int r = Jv - 1; r >= R; --r) tail += val(r);
+            for (int r = Jv - 1; r >= R; --r) tail += vals[r];
         } else {
+            // R = Jv; while (R > 1 && tail + val(R - 1) <= tau) tail += val(--R),
+            // with the values loaded eight at a time ahead of the running sum
             R = Jv;
-            while (R > 1 && tail + val(R - 1) <= tau) {
-                tail += val(R - 1);
-                --R;
+            bool more = true;
+            double vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vb[u] = vals[max(R - 1 - u, 0)];  // unused past r = 1
+            while (more) {
+                double nb8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) nb8[u] = vals[max(R - 9 - u, 0)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double t = tail + vb[u];
+                    more = more && R > 1 && t <= tau;
+                    tail = more ? t : tail;
+                    R -= more ? 1 : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) vb[u] = nb8[u];
             }
         }
         double bound = 0.0;
@@ -684,8 +734,8 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
             // tail sums (EigArgs::guard): a model standard deviation at each
             // side, sqrt(4 delta^2 t + 2 K delta^4 (J - r)) for the tail t
             // beyond rank r.  R = J discards nothing and is exact.
-            const double d2 = a.split_stats[0];
-            const double dl2 = ldexp(1.0, 2 * ((int)a.split_stats[1] - 16)) / 3.0;
+            const double d2 = stat_d2;
+            const double dl2 = ldexp(1.0, 2 * ((int)stat_e - 16)) / 3.0;
             auto margin = [&](double t, int r) {
                 return a.guard * sqrt(4.0 * dl2 * t + 2.0 * a.ncols * dl2 * dl2 * (double)(Jv - r)) +
                        kSplitModelError * d2;
@@ -710,10 +760,21 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
         misc[0] = R;
         // shifts for inverse iteration: separate (near-)equal eigenvalues
         const double pert = 10.0 * DBL_EPSILON * tnorm;
-        for (int j = 0; j < R; ++j) {
-            double sj = lam[j];
-            if (j > 0 && shift[j - 1] - sj < pert) sj = shift[j - 1] - pert;
-            shift[j] = sj;
+        double prev = 0.0;
+        for (int j0 = 0; j0 < R; j0 += 8) {
+            double lb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) lb[u] = lam[min(j0 + u, R - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u;
+                if (j < R) {
+                    double sj = lb[u];
+                    if (j > 0 && prev - sj < pert) sj = prev - pert;
+                    shift[j] = sj;
+                    prev = sj;
+                }
+            }
         }
     }
     __syncthreads();
@@ -721,167 +782,381 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
 
 
     // ---- 4. inverse iteration, batches of vectors held in LDS -----------
+    // One thread per vector runs the recurrences on a record of its own in
+    // LDS: row i holds (x, reciprocal pivot, u1, u2, multiplier, pivot flag)
+    // at rec[kLuArrays i ..], so every access is the thread's base plus an
+    // immediate offset; the record's last double is x of row Jb (zero), and
+    // records are an odd number of doubles apart, which keeps the lanes of a
+    // wave in distinct banks.  Loads are never conditional (a guarded load
+    // waits for its value inside the guard).  Operands are read a block
+    // of kSweepRows rows ahead of the recurrence (a load that follows a store
+    // to the same record waits for it), and rows are padded to whole blocks
+    // with exact zeros, which every sweep maps to zeros.  A sweep's
+    // normalisation is applied when the next sweep (or the copy-out) reads
+    // its result, with the same two roundings as an in-place pass.
     const double tiny = DBL_EPSILON * tnorm + DBL_MIN;
-    const int batch = (int)((size_t)region / ((size_t)kLuArrays * J));
+    const int Jb = eig_sweep_rows(J);
+    const int recd = kLuArrays * Jb + 1;  // doubles per record
+    const int batch = (int)((size_t)region / ((size_t)recd + 2));
+    constexpr int oX = 0, oRP = 1, oU1 = 2, oU2 = 3, oLM = 4, oPV = 5;
     for (int j0 = 0; j0 < R; j0 += batch) {
         const int nb = min(batch, R - j0);
-        // per-vector arrays, element i of vector jj at [array][i][jj]
-        double* RU0 = reg;
-        double* U1 = RU0 + (size_t)J * nb;
-        double* U2 = U1 + (size_t)J * nb;
-        double* LM = U2 + (size_t)J * nb;
-        double* PV = LM + (size_t)J * nb;
-        double* XV = PV + (size_t)J * nb;
+        double* SC1 = reg + (size_t)recd * nb;  // nb: pending scale factors of x
+        double* SC2 = SC1 + nb;
         __syncthreads();  // the region is free (A or the previous batch)
+        // deterministic start vectors, zero in the padding rows and row Jb
+        for (int idx = tid; idx < (Jb + 1) * nb; idx += kEigThreads) {
+            const int jj = idx / (Jb + 1), i = idx - jj * (Jb + 1);
+            reg[(size_t)jj * recd + kLuArrays * i + oX] =
+                i < J ? hash_unit((uint32_t)(j0 + jj), (uint32_t)i) : 0.0;
+        }
+        __syncthreads();
         if (tid < nb) {
+            constexpr int IB = kSweepRows;
+            constexpr int W = kLuArrays;
             const int jj = tid, j = j0 + tid;
+            double* rec = reg + (size_t)jj * recd;
+            // Row i0 of the record.  The offset goes through an empty asm so
+            // that each block forms one address and reaches its rows by
+            // immediate offsets (the compiler otherwise keeps one address per
+            // row and field across the sweep loops).
+            auto row = [&](int i0) {
+                int o = W * i0;
+                asm volatile("" : "+s"(o));
+                return rec + o;
+            };
             const double sg = shift[j];
+            const double rtiny = recip(tiny);  // recip(-tiny) = -recip(tiny) exactly
+            // LU factorisation of T - sg I with partial pivoting
             double ai = d[0] - sg, bi = (J > 1) ? e[0] : 0.0;
-            for (int i = 0; i + 1 < J; ++i) {
-                const double ci = e[i];
-                const double an = d[i + 1] - sg;
-                const double bn = (i + 2 < J) ? e[i + 1] : 0.0;
-                double u1, u2, l, pf, rp;
-                if (fabs(ai) >= fabs(ci)) {
-                    double piv = ai;
-                    u1 = bi;
-                    u2 = 0.0;
-                    if (fabs(piv) < tiny) piv = (piv < 0.0 ? -tiny : tiny);
-                    rp = recip(piv);
-                    l = ci * rp;
-                    pf = 0.0;
-                    ai = an - l * bi;
-                    bi = bn;
-                } else {
-                    double piv = ci;  // |ci| > |ai| >= 0
-                    u1 = an;
-                    u2 = bn;
-                    rp = recip(piv);
-                    l = ai * rp;
-                    pf = 1.0;
-                    ai = bi - l * an;
-                    bi = -l * bn;
-                    if (fabs(piv) < tiny) rp = recip(piv < 0.0 ? -tiny : tiny);
+            for (int i0 = 0; i0 + 1 < J; i0 += IB) {
+                double cb[IB], anb[IB], bnb[IB];
+#pragma unroll
+                for (int u = 0; u < IB; ++u) {
+                    const int i = min(i0 + u, J - 2);
+                    cb[u] = e[i];
+                    anb[u] = d[i + 1] - sg;
+                    const double en = e[i + 1];
+                    bnb[u] = (i + 2 < J) ? en : 0.0;
                 }
-                RU0[i * nb + jj] = rp;
-                U1[i * nb + jj] = u1;
-                U2[i * nb + jj] = u2;
-                LM[i * nb + jj] = l;
-                PV[i * nb + jj] = pf;
+                double* rr = row(i0);
+#pragma unroll
+                for (int u = 0; u < IB; ++u) {
+                    if (i0 + u + 1 < J) {  // uniform
+                        // Without interchange (|a_i| >= |c_i|) the pivot is a_i,
+                        // raised to +-tiny if smaller; with it the pivot is c_i
+                        // (|c_i| > |a_i|), the multiplier uses c_i itself and only
+                        // the stored reciprocal is that of +-tiny.  Selects, not
+                        // branches: lanes of a wave take either case.
+                        const double ci = cb[u], an = anb[u], bn = bnb[u];
+                        const bool keep = fabs(ai) >= fabs(ci);
+                        const double pa = fabs(ai) < tiny ? (ai < 0.0 ? -tiny : tiny) : ai;
+                        const double rl = recip(keep ? pa : ci);
+                        const double l = (keep ? ci : ai) * rl;
+                        const double rp = (!keep && fabs(ci) < tiny) ? (ci < 0.0 ? -rtiny : rtiny) : rl;
+                        const double u1 = keep ? bi : an;
+                        const double u2 = keep ? 0.0 : bn;
+                        const double pf = keep ? 0.0 : 1.0;
+                        const double ain = keep ? an - l * bi : bi - l * an;
+                        bi = keep ? bn : -l * bn;
+                        ai = ain;
+                        rr[W * u + oRP] = rp;
+                        rr[W * u + oU1] = u1;
+                        rr[W * u + oU2] = u2;
+                        rr[W * u + oLM] = l;
+                        rr[W * u + oPV] = pf;
+                    }
+                }
             }
             if (fabs(ai) < tiny) ai = (ai < 0.0 ? -tiny : tiny);
-            RU0[(J - 1) * nb + jj] = recip(ai);
-            // the last row has no superdiagonal terms; back substitution
-            // reads them (times zero), so they must not be stale LDS
-            U1[(J - 1) * nb + jj] = 0.0;
-            U2[(J - 1) * nb + jj] = 0.0;
-#pragma unroll 4
-            for (int i = 0; i < J; ++i) XV[i * nb + jj] = hash_unit((uint32_t)j, (uint32_t)i);
+            // The last row has no superdiagonal terms and no multiplier; the
+            // padding rows are all zero (their pivot reciprocal included).
+            for (int i = J - 1; i < Jb; ++i) {
+                rec[W * i + oRP] = i == J - 1 ? recip(ai) : 0.0;
+                rec[W * i + oU1] = 0.0;
+                rec[W * i + oU2] = 0.0;
+                rec[W * i + oLM] = 0.0;
+                rec[W * i + oPV] = 0.0;
+            }
+            double f1 = 1.0, f2 = 1.0;  // x = (stored x f1) f2
+            // Both sweeps alternate two register sets: the next block's loads
+            // are issued before this block's arithmetic and stores.  Rows past
+            // J (all in the last block) carry zeros: the forward sweep maps a
+            // zero row to zero, the backward one forces them.
             for (int it = 0; it < kInvIters; ++it) {
                 // forward: row interchanges and multipliers, running value in xc
-                double xc = XV[jj];
-#pragma unroll 4
-                for (int i = 0; i + 1 < J; ++i) {
-                    double xn = XV[(i + 1) * nb + jj];
-                    if (PV[i * nb + jj] != 0.0) {
-                        const double t = xc;
-                        xc = xn;
-                        xn = t;
+                double xA[IB], pA[IB], lA[IB], xB[IB], pB[IB], lB[IB];
+                auto fload = [&](int i0, double (&xb)[IB], double (&pb)[IB], double (&lb)[IB]) {
+                    const double* rr = row(i0);
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) {
+                        xb[u] = (rr[W * (u + 1) + oX] * f1) * f2;  // row Jb: zero
+                        pb[u] = rr[W * u + oPV];
+                        lb[u] = rr[W * u + oLM];
                     }
-                    XV[i * nb + jj] = xc;
-                    xc = xn - LM[i * nb + jj] * xc;
+                };
+                double xc = (rec[oX] * f1) * f2;
+                auto fstep = [&](int i0, const double (&xb)[IB], const double (&pb)[IB],
+                                 const double (&lb)[IB]) {
+                    double ob[IB];
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) {
+                        double xn = xb[u];
+                        if (pb[u] != 0.0) {
+                            const double t = xc;
+                            xc = xn;
+                            xn = t;
+                        }
+                        ob[u] = xc;
+                        xc = xn - lb[u] * xc;
+                    }
+                    double* rw = row(i0);
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) rw[W * u + oX] = ob[u];
+                };
+                fload(0, xA, pA, lA);
+                for (int i0 = 0;; i0 += 2 * IB) {
+                    fload(min(i0 + IB, Jb - IB), xB, pB, lB);
+                    fstep(i0, xA, pA, lA);
+                    if (i0 + IB >= Jb) break;
+                    fload(min(i0 + 2 * IB, Jb - IB), xA, pA, lA);
+                    fstep(i0 + IB, xB, pB, lB);
+                    if (i0 + 2 * IB >= Jb) break;
                 }
-                XV[(J - 1) * nb + jj] = xc;
                 // backward substitution
+                double u1A[IB], u2A[IB], rA[IB], u1B[IB], u2B[IB], rB[IB];
+                auto bload = [&](int i0, double (&xb)[IB], double (&u1b)[IB], double (&u2b)[IB],
+                                 double (&rb)[IB]) {
+                    const double* rr = row(i0);
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) {
+                        xb[u] = rr[W * u + oX];
+                        u1b[u] = rr[W * u + oU1];
+                        u2b[u] = rr[W * u + oU2];
+                        rb[u] = rr[W * u + oRP];
+                    }
+                };
                 double x1 = 0.0, x2 = 0.0, amax = 0.0;
-#pragma unroll 4
-                for (int i = J - 1; i >= 0; --i) {
-                    double v = XV[i * nb + jj];
-                    v = fma(-U1[i * nb + jj], x1, v);
-                    v = fma(-U2[i * nb + jj], x2, v);
-                    v *= RU0[i * nb + jj];
-                    XV[i * nb + jj] = v;
-                    x2 = x1;
-                    x1 = v;
-                    amax = fmax(amax, fabs(v));
+                auto bstep = [&](auto top, int i0, const double (&xb)[IB], const double (&u1b)[IB],
+                                 const double (&u2b)[IB], const double (&rb)[IB]) {
+                    double ob[IB];
+#pragma unroll
+                    for (int u = IB - 1; u >= 0; --u) {
+                        double v = xb[u];
+                        v = fma(-u1b[u], x1, v);
+                        v = fma(-u2b[u], x2, v);
+                        v *= rb[u];
+                        if constexpr (decltype(top)::value) v = i0 + u < J ? v : 0.0;
+                        ob[u] = v;
+                        x2 = x1;
+                        x1 = v;
+                        amax = fmax(amax, fabs(v));
+                    }
+                    double* rw = row(i0);
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) rw[W * u + oX] = ob[u];
+                };
+                bload(Jb - IB, xA, u1A, u2A, rA);
+                for (int i0 = Jb - IB;; i0 -= 2 * IB) {
+                    bload(max(i0 - IB, 0), xB, u1B, u2B, rB);
+                    if (i0 == Jb - IB)
+                        bstep(std::true_type{}, i0, xA, u1A, u2A, rA);
+                    else
+                        bstep(std::false_type{}, i0, xA, u1A, u2A, rA);
+                    if (i0 == 0) break;
+                    bload(max(i0 - 2 * IB, 0), xA, u1A, u2A, rA);
+                    bstep(std::false_type{}, i0 - IB, xB, u1B, u2B, rB);
+                    if (i0 == IB) break;
                 }
                 double nrm2 = 0.0;
                 const double scl = amax > 0.0 ? 1.0 / amax : 1.0;
 #pragma unroll 8
                 for (int i = 0; i < J; ++i) {
-                    const double v = XV[i * nb + jj] * scl;
-                    XV[i * nb + jj] = v;
+                    const double v = rec[W * i + oX] * scl;
                     nrm2 += v * v;
                 }
-                const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-#pragma unroll 8
-                for (int i = 0; i < J; ++i) XV[i * nb + jj] *= inv;
+                f1 = scl;
+                f2 = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
             }
+            SC1[jj] = f1;
+            SC2[jj] = f2;
         }
         __syncthreads();
         for (int idx = tid; idx < J * nb; idx += kEigThreads) {
             const int jj = idx / J, i = idx - jj * J;
-            X[(size_t)(j0 + jj) * J + i] = XV[i * nb + jj];
+            X[(size_t)(j0 + jj) * J + i] =
+                (reg[(size_t)jj * recd + kLuArrays * i + oX] * SC1[jj]) * SC2[jj];
         }
     }
     __syncthreads();
 
-    // modified Gram-Schmidt, twice, inside clusters (descending order), by
-    // wave 0 with the working vectors in registers
+    // Modified Gram-Schmidt, twice, inside clusters (descending order), by
+    // wave 0 with the working vector in registers and the others in LDS;
+    // cluster starts are found in one pass over the eigenvalues.
     const int nslot = (J + 63) / 64;
+    // per-lane slots of a vector: JP / 64 on the register path (at least 1)
+    constexpr int kGsSlots = JP > 0 ? (JP >= 64 ? JP / 64 : 1) : kMaxVecSlots;
     const double ortol = 1e-3 * tnorm;
-    if (wave == 0) {
-        for (int j = 1; j < R; ++j) {
-            int c0 = j;
-            while (c0 > 0 && lam[c0 - 1] - lam[c0] <= ortol) --c0;
-            if (c0 == j) continue;
-            double xj[kMaxVecSlots];
+    const bool clustered =
+        __syncthreads_or(tid >= 1 && tid < R && lam[tid - 1] - lam[tid] <= ortol);
+    if (clustered) {
+        // vector j at XL[j J ..]: a copy in LDS when the region holds all R
+        const bool in_lds = (size_t)R * J <= (size_t)region;
+        double* XL = in_lds ? reg : X;
+        if (in_lds)
+            for (int idx = tid; idx < R * J; idx += kEigThreads) XL[idx] = X[idx];
+        __syncthreads();
+        if (wave == 0) {
+            int c0 = 0;
+            for (int j = 1; j < R; ++j) {
+                c0 = lam[j - 1] - lam[j] <= ortol ? c0 : j;
+                if (c0 == j) continue;
+                // slot q holds element lane + 64 q (zero past J; the load
+                // itself is clamped to the vector)
+                auto ld = [&](int v, int q) {
+                    const int t = lane + 64 * q;
+                    const double x = XL[(size_t)v * J + min(t, J - 1)];
+                    return t < J ? x : 0.0;
+                };
+                double xj[kGsSlots];
 #pragma unroll
-            for (int q = 0; q < kMaxVecSlots; ++q) {
-                const int t = lane + 64 * q;
-                xj[q] = (q < nslot && t < J) ? X[(size_t)j * J + t] : 0.0;
-            }
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int i = c0; i < j; ++i) {
-                    double xi[kMaxVecSlots];
-                    double s = 0.0;
+                for (int q = 0; q < kGsSlots; ++q) xj[q] = q < nslot ? ld(j, q) : 0.0;
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int i = c0; i < j; ++i) {
+                        double xi[kGsSlots];
+                        double s = 0.0;
 #pragma unroll
-                    for (int q = 0; q < kMaxVecSlots; ++q) {
-                        const int t = lane + 64 * q;
-                        xi[q] = (q < nslot && t < J) ? X[(size_t)i * J + t] : 0.0;
-                        s += xi[q] * xj[q];
+                        for (int q = 0; q < kGsSlots; ++q) {
+                            xi[q] = q < nslot ? ld(i, q) : 0.0;
+                            s += xi[q] * xj[q];
+                        }
+                        s = wave_sum(s);
+#pragma unroll
+                        for (int q = 0; q < kGsSlots; ++q) xj[q] -= s * xi[q];
                     }
-                    s = wave_sum(s);
-#pragma unroll
-                    for (int q = 0; q < kMaxVecSlots; ++q) xj[q] -= s * xi[q];
                 }
-            }
-            double n2 = 0.0;
+                double n2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < kMaxVecSlots; ++q) n2 += xj[q] * xj[q];
-            n2 = wave_sum(n2);
-            const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+                for (int q = 0; q < kGsSlots; ++q) n2 += xj[q] * xj[q];
+                n2 = wave_sum(n2);
+                const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
 #pragma unroll
-            for (int q = 0; q < kMaxVecSlots; ++q) {
-                const int t = lane + 64 * q;
-                if (q < nslot && t < J) X[(size_t)j * J + t] = xj[q] * inv;
+                for (int q = 0; q < kGsSlots; ++q) {
+                    const int t = lane + 64 * q;
+                    if (q < nslot && t < J) XL[(size_t)j * J + t] = xj[q] * inv;
+                }
+                if (!in_lds) __threadfence_block();  // later iterations read column j
             }
-            __threadfence_block();  // later iterations of this wave read column j
         }
+        __syncthreads();
+        if (in_lds)
+            for (int idx = tid; idx < R * J; idx += kEigThreads) X[idx] = XL[idx];
     }
     __syncthreads();
 
     // ---- 5. back-transformation X <- Q X, Q = H_0 H_1 ... H_{J-3} -------
-    // With A in registers (J <= JP) the LDS region, free again after the
-    // inverse iteration, holds all reflectors: copy them back in one
-    // coalesced pass so that the loop below reads LDS instead of issuing a
-    // dependent global load per reflector.
-    const double* Hb = H;
+    // Sign rule for every vector: the largest |entry| (lowest index on ties)
+    // is positive.
     if constexpr (JP > 0) {
-        for (int idx = tid; idx < (J - 2) * J; idx += kEigThreads) reg[idx] = H[idx];
+        // A in registers (J <= JP): the LDS region, free again, takes the
+        // reflectors in one coalesced pass at pitch JP with zeros outside
+        // k < t < J (Hz[k JP + t] = v_t of reflector k).  Each vector is held
+        // by 16 lanes, element t = 32 p + 2 l + h at lane l, pair p, half h,
+        // so that a dot product ends in four row-local lane exchanges; a wave
+        // carries four vectors through the J - 2 reflectors without barriers.
+        constexpr int NP = JP / 32;
+        double* Hz = reg;
+        for (int idx = tid; idx < (J - 2) * JP; idx += kEigThreads) {
+            const int k = idx / JP, t = idx - k * JP;
+            Hz[idx] = (t > k && t < J) ? H[(size_t)k * J + (t - k - 1)] : 0.0;
+        }
         __syncthreads();
-        Hb = reg;
-    }
+        const int g = lane >> 4, l16 = lane & 15;
+        for (int jw = 4 * wave; jw < R; jw += 4 * kEigWaves) {  // uniform over the wave
+            const int j = jw + g;
+            const bool jok = j < R;
+            double2 xr[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int t = 32 * p + 2 * l16;
+                xr[p].x = (jok && t < J) ? X[(size_t)j * J + t] : 0.0;
+                xr[p].y = (jok && t + 1 < J) ? X[(size_t)j * J + t + 1] : 0.0;
+            }
+            // reflector k and beta_k are loaded one reflector ahead of their use
+            auto hload = [&](int k, double2 (&h)[NP], double& b) {
+                b = beta[k];
+                const double2* hk = reinterpret_cast<const double2*>(Hz + (size_t)k * JP);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) h[p] = hk[16 * p + l16];
+            };
+            auto apply = [&](const double2 (&h)[NP], double b) {
+                if (b == 0.0) return;  // uniform: the identity
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    s0 = fma(h[p].x, xr[p].x, s0);
+                    s1 = fma(h[p].y, xr[p].y, s1);
+                }
+                const double sk = b * row16_sum(s0 + s1);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    xr[p].x -= sk * h[p].x;
+                    xr[p].y -= sk * h[p].y;
+                }
+            };
+            if (J >= 3) {
+                double2 hA[NP], hB[NP];
+                double bA, bB;
+                hload(J - 3, hA, bA);
+                for (int k = J - 3;; k -= 2) {
+                    hload(max(k - 1, 0), hB, bB);
+                    apply(hA, bA);
+                    if (k == 0) break;
+                    hload(max(k - 2, 0), hA, bA);
+                    apply(hB, bB);
+                    if (k == 1) break;
+                }
+            }
+            double bv = -1.0;
+            int bi = J;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int t = 32 * p + 2 * l16;
+                if (t < J && fabs(xr[p].x) > bv) {
+                    bv = fabs(xr[p].x);
+                    bi = t;
+                }
+                if (t + 1 < J && fabs(xr[p].y) > bv) {
+                    bv = fabs(xr[p].y);
+                    bi = t + 1;
+                }
+            }
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {  // within the 16-lane group
+                const double ov = __shfl_xor(bv, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            double at = 0.0;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int t = 32 * p + 2 * l16;
+                if (t == bi) at = xr[p].x;
+                if (t + 1 == bi) at = xr[p].y;
+            }
+            const double sgn = row16_sum(at) < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int t = 32 * p + 2 * l16;
+                if (jok && t < J) X[(size_t)j * J + t] = sgn * xr[p].x;
+                if (jok && t + 1 < J) X[(size_t)j * J + t + 1] = sgn * xr[p].y;
+            }
+        }
+    } else {
+    // reflectors from global scratch; one wave per vector
     for (int j = wave; j < R; j += kEigWaves) {
         double xr[kMaxVecSlots];
 #pragma unroll
@@ -897,14 +1172,13 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
 #pragma unroll
             for (int q = 0; q < kMaxVecSlots; ++q) {
                 const int t = lane + 64 * q;
-                hv[q] = (q < nslot && t > k && t < J) ? Hb[(size_t)k * J + (t - k - 1)] : 0.0;
+                hv[q] = (q < nslot && t > k && t < J) ? H[(size_t)k * J + (t - k - 1)] : 0.0;
                 s += hv[q] * xr[q];
             }
             s = b * wave_sum(s);
 #pragma unroll
             for (int q = 0; q < kMaxVecSlots; ++q) xr[q] -= s * hv[q];
         }
-        // sign rule: the largest |entry| (lowest index on ties) is positive
         double bv = -1.0;
         int bi = J;
 #pragma unroll
@@ -934,6 +1208,7 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
             const int t = lane + 64 * q;
             if (q < nslot && t < J) X[(size_t)j * J + t] = sgn * xr[q];
         }
+    }
     }
 }
 
