@@ -3,9 +3,8 @@
 // this is the same family of method on one workgroup):
 //
 //   1. Householder reduction to tridiagonal form T = Q^T S Q.  Each step
-//      forms A22 x (x = the pivot row) and |x|^2 in one pass, derives the
-//      reflector, then applies the symmetric rank-2 update with a
-//      commutative formula so A stays exactly symmetric.  For J <= 128 the
+//      derives the reflector from the pivot row, forms p = tau A22 v, then
+//      applies the rank-2 update A22 -= v w^T + w v^T.  For J <= 128 the
 //      matrix lives in registers; otherwise it lives in global scratch and
 //      the first J - 128 columns are reduced in panels of eight (the rank-2
 //      updates of a panel are kept as vectors in LDS, applied to the pivot
@@ -229,20 +228,14 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
     // that entries no step writes are exact zeros: reflector k is written
     // from column k + 1 on) and four JP-long vector buffers in the
     // 1024-double area after misc (zeroed too; the global-A path alone uses
-    // it otherwise).  A's diagonal and superdiagonal are kept beside the
-    // registers in LDS (dg, sd), updated by lane 0 of each row with the same
-    // formula as the registers, so that the pivot's a_kk and a_k,k+1 are an
-    // LDS read rather than a register chosen by a run-time index.  Finished
-    // rows and columns see v = p = 0, so the register loops need no masks.
-    static_assert(6 * JP <= kEigThreads, "vector buffers must fit the partial-sum area");
+    // it otherwise).  Finished rows and columns see v = p = 0, so the
+    // register loops need no masks.  Each column reads v and p from LDS by
+    // every row, which bounds the step: from block KEEP on v, and from KEEP2
+    // on p, stay in registers between the matrix-vector product and the
+    // update (the live chunks shrink with the block index).
+    static_assert(4 * JP <= kEigThreads, "vector buffers must fit the partial-sum area");
     double* vbuf = red + 64 + 8;
-    double* dg = vbuf + 4 * JP;
-    double* sd = dg + JP;
     for (int i = tid; i < 4 * JP; i += kEigThreads) vbuf[i] = 0.0;
-    for (int i = tid; i < JP; i += kEigThreads) {
-        dg[i] = i < Jr ? src[i + (size_t)ld * i] : 0.0;
-        sd[i] = i + 1 < Jr ? src[i + (size_t)ld * (i + 1)] : 0.0;
-    }
     for (int i = tid; i < (Jr > 2 ? Jr - 2 : 0) * JP; i += kEigThreads) Hs[i] = 0.0;
     __syncthreads();
     // Columns run in blocks of eight, the block index KB a compile-time
@@ -275,7 +268,12 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
                     sq[q & 3] = fma(m, m, sq[q & 3]);
                 }
                 const double sigma = row8_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
-                const double x0 = sd[k], akk = dg[k];
+                // a_kk and a_k,k+1 from the lanes of row k that hold them:
+                // column k lies in chunk KB, column k + 1 in KB or KB + 1
+                const int l0 = 8 * (k & 7);
+                const double akk = read_lane(av[KB], l0 + (k & 7));
+                const double x0 = read_lane(((k + 1) >> 3) == KB ? av[KB] : av[KB + 1 < NQ ? KB + 1 : KB],
+                                            l0 + ((k + 1) & 7));
                 double tau = 0.0, alpha = x0, inv_v0 = 0.0;
                 if (sigma != 0.0) {
                     const double ss = fma(x0, x0, sigma);
@@ -301,45 +299,63 @@ __device__ __forceinline__ void tridiag_regs(const double* __restrict__ src, int
             }
             __syncthreads();
             const double tau = *sg;
-            if (tau == 0.0) continue;  // uniform: the reflector is the identity
             // A wave whose 8 rows are all <= k has nothing to form or update (uniform).
             const bool wact = 8 * wave + 7 > k;
             double part = 0.0;
-            if (wact) {
+            constexpr int KEEP = 2, KEEP2 = 4;
+            double vq[NQ];
+            if (wact) {  // formed before tau is tested, so that v's loads do not wait for it
                 double pr[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int q = KB; q < NQ; ++q) pr[q & 3] = fma(av[q], vs[rc + 8 * q], pr[q & 3]);
+                for (int q = KB; q < NQ; ++q) {
+                    vq[q] = vs[rc + 8 * q];
+                    pr[q & 3] = fma(av[q], vq[q], pr[q & 3]);
+                }
                 part = row8_sum((pr[0] + pr[1]) + (pr[2] + pr[3]));  // (A22 v)_i
             }
+            if (tau == 0.0) continue;  // uniform: the reflector is the identity
             if (rc == 0 && ri < JP) ps[ri] = (wact && ri > k && rowok) ? tau * part : 0.0;
             __syncthreads();
             if (!wact) continue;  // uniform over the wave; it still meets every barrier
-            // A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v.  Every wave
-            // forms p.v with the same bits, and w_i, w_j come from the same
-            // formula on the same values, so A stays exactly symmetric;
-            // entries outside the trailing block see v = w = 0.
-            double pv = 0.0;
+            // A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v, two fused
+            // multiply-adds per element; entries outside the trailing block
+            // see v = w = 0.  Every lane forms p.v with the same bits (from
+            // KEEP2 on as a sum over its row's 8 lanes, all rows holding the
+            // same values).  The update rounds a_ij and a_ji differently, so
+            // A is symmetric up to rounding; only each row's own elements are
+            // ever read, so the reduction is that of a matrix within rounding
+            // of the exact iterate.
+            double pq[NQ];
+            double half;
+            if constexpr (KB >= KEEP2) {
+                double pr2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int r = 0; r < NS; ++r) {
-                const int j = lane + 64 * r;
-                if (j < JP) pv = fma(ps[j], vs[j], pv);
+                for (int q = KB; q < NQ; ++q) {
+                    pq[q] = ps[rc + 8 * q];
+                    pr2[q & 3] = fma(pq[q], vq[q], pr2[q & 3]);
+                }
+                half = 0.5 * tau * row8_sum((pr2[0] + pr2[1]) + (pr2[2] + pr2[3]));
+            } else {
+                double pv = 0.0;
+#pragma unroll
+                for (int r = 0; r < NS; ++r) {
+                    const int j = lane + 64 * r;
+                    if (j < JP) pv = fma(ps[j], vs[j], pv);
+                }
+                half = 0.5 * tau * wave_sum(pv);
             }
-            const double half = 0.5 * tau * wave_sum(pv);
             const int ric = ri < JP ? ri : 0;
             const double vi = vs[ric], wi = fma(-half, vi, ps[ric]);
 #pragma unroll
             for (int q = KB; q < NQ; ++q) {
-                const double vj = vs[rc + 8 * q];
-                const double wj = fma(-half, vj, ps[rc + 8 * q]);
-                av[q] -= __dadd_rn(__dmul_rn(vi, wj), __dmul_rn(wi, vj));
-            }
-            // the same update of a_ii and a_i,i+1 beside the registers
-            if (rc == 0 && ri > k && rowok) {
-                dg[ri] -= __dadd_rn(__dmul_rn(vi, wi), __dmul_rn(wi, vi));
-                if (ri + 1 < Jr) {
-                    const double v1 = vs[ri + 1], w1 = fma(-half, v1, ps[ri + 1]);
-                    sd[ri] -= __dadd_rn(__dmul_rn(vi, w1), __dmul_rn(wi, v1));
-                }
+                double vj;
+                if constexpr (KB >= KEEP) vj = vq[q];
+                else vj = vs[rc + 8 * q];
+                double pj;
+                if constexpr (KB >= KEEP2) pj = pq[q];
+                else pj = ps[rc + 8 * q];
+                const double wj = fma(-half, vj, pj);
+                av[q] = fma(-wi, vj, fma(-vi, wj, av[q]));
             }
         }
     });
