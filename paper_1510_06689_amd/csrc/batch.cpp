@@ -40,6 +40,16 @@ struct GramLaunch {
 // Gram's intensity on FP32 data is below the FP64 matrix-core ridge, so it
 // costs no more than the split Gram, and its rank needs no guard.
 bool f64_class(int jb) { return jb <= 32; }
+
+// From the second step on, a problem of a split class whose FP64 Gram takes
+// at most this many flops (2 K J^2 at its actual shape, known on the device
+// only) is marked before the Grams (status bit 8) and takes the FP64 Gram
+// instead of the split one.  A truncated unfolding's rows span a wide range
+// of magnitudes, so the 16-bit split's error bound often cannot certify its
+// rank, and for a small problem the split Gram plus an FP64 redo costs more
+// than the FP64 Gram alone.  Marked problems take the same reduction and
+// eigensolver launches as the others, so the step keeps one eigensolver pass.
+constexpr double kBatchF64Flops = 6e7;
 struct TtmLaunch {
     int J, kmax, ntasks, total_wg;
     size_t off;
@@ -407,12 +417,19 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
     for (int s = 0; s < h->N; ++s) {
         const StepPlan& sp = h->steps[s];
         bool split = false;
+        if (h->guarded && s > 0)
+            for (const GramLaunch& g : sp.grams)
+                if (!g.f64)
+                    TK_TRY(launch_batch_mark_fp64((const BatchGramTask*)(h->tables_dev + g.off),
+                                                  g.ntasks, kBatchF64Flops, st));
         for (const GramLaunch& g : sp.grams) {
             const BatchGramTask* tasks = (const BatchGramTask*)(h->tables_dev + g.off);
             if (g.f64) {
                 TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 0, st));
             } else {
                 TK_TRY(launch_gram_split_batched(tasks, g.ntasks, g.total_wg, g.jb, st));
+                if (h->guarded && s > 0)
+                    TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 2, st));
                 split = true;
             }
         }

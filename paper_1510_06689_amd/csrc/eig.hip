@@ -1285,37 +1285,43 @@ constexpr int kBatchTpe = 16;
 constexpr int kBatchGroups = 64 / kBatchTpe;
 
 __global__ __launch_bounds__(64) void eig_multisect_batched(const EigArgs* __restrict__ args,
-                                                            int nq) {
+                                                            int nq, int conditional) {
     extern __shared__ double sm[];
     const int p = blockIdx.x / nq, q = blockIdx.x - p * nq;
     const int J = args[p].J;
     if (kBatchGroups * q >= J) return;  // uniform over the workgroup
+    if (conditional && !(args[p].flags[0] & 4)) return;  // the redo pass: bit 4 only
     const int k = kBatchGroups * q + (int)threadIdx.x / kBatchTpe;
     multisect_group<kBatchTpe>(eig_handoff(args[p].scratch, J), J, k, k < J, sm);
 }
 
-// One workgroup per problem of a batch.  conditional != 0: only problems whose
-// status word has the guard bit (4) run, on their FP64 Gram and without the
-// guard; afterwards the bit is cleared and `mode_bit` is recorded in the
-// problem's second status word.  PH as in eig_body: the unconditional pass
-// runs as PH = 1, eig_multisect_batched, PH = 3; the conditional one, which
-// few problems take, as one launch (PH = 0).
+// One workgroup per problem of a batch, as PH = 1, eig_multisect_batched,
+// PH = 3.  A problem whose status word has the FP64-only mark (8) took the
+// FP64 Gram: the plain rank rule applies, and the pass's last launch clears
+// the mark.  conditional != 0: only problems whose status word has the guard
+// bit (4) run, on their FP64 Gram and without the guard; afterwards the bit is
+// cleared and `mode_bit` is recorded in the problem's second status word.
 template <int JP, int PH>
 __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __restrict__ args,
                                                            int region, int conditional,
                                                            int mode_bit) {
     EigArgs a = args[blockIdx.x];
-    if (conditional) {
-        if (!(a.flags[0] & 4)) return;  // uniform over the workgroup
-        a.guard = 0.0;                  // an FP64 Gram: plain rank rule
+    const int f0 = a.flags ? a.flags[0] : 0;
+    if (conditional && !(f0 & 4)) return;  // uniform over the workgroup
+    if (conditional || (f0 & 8)) {
+        a.guard = 0.0;  // an FP64 Gram: plain rank rule
         a.split_stats = nullptr;
     }
     eig_body<JP, PH>(a, region);
-    if (conditional) {
+    if (PH != 1 && (conditional || (f0 & 8))) {  // the pass's last launch
         __syncthreads();
         if (threadIdx.x == 0) {
-            a.flags[0] &= ~4;
-            a.flags[1] |= mode_bit;
+            if (conditional) {
+                a.flags[0] &= ~4;
+                a.flags[1] |= mode_bit;
+            } else {
+                a.flags[0] &= ~8;
+            }
         }
     }
 }
@@ -1347,11 +1353,10 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
         TK_HIP(hipGetLastError());
         return TK_OK;
     };
-    if (conditional) return launch(eig_batched<128, 0>);
     TK_TRY(launch(eig_batched<128, 1>));
     const int nq = (jmax + kBatchGroups - 1) / kBatchGroups;
     hipLaunchKernelGGL(eig_multisect_batched, dim3(count * nq), dim3(64),
-                       (size_t)2 * jmax * sizeof(double), st, args_dev, nq);
+                       (size_t)2 * jmax * sizeof(double), st, args_dev, nq, conditional);
     TK_HIP(hipGetLastError());
     return launch(eig_batched<128, 3>);
 }

@@ -514,7 +514,9 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int n = tk.npairs * 256;
     const int P = *tk.nparts;  // slots the Gram launch wrote (<= tk.P)
-    const bool extra = tk.nu != nullptr || (tk.aux != nullptr && !conditional);
+    // split statistics: a split Gram's, not a redo's nor an FP64-only problem's
+    const bool split = tk.aux != nullptr && !conditional && !(tk.status && (*tk.status & 8));
+    const bool extra = tk.nu != nullptr || split;
     if (w < tk.nwg - 1 || !extra) {
         const int idx = w * 64 + o;
         const double acc = idx < n ? sum_partials(tk.partial, P, n, idx, g) : 0.0;
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
         // the problem's last workgroup: split statistics of the unconditional
         // (split) pass, and the trace of its diagonal from the partials
         // (diagonal 16-blocks p = bi nb - bi (bi - 1) / 2), fixed order
-        if (tk.aux != nullptr && !conditional) {
+        if (split) {
             reduce_split_stats(tk.aux, P, tk.stats, &part[0][0]);
             __syncthreads();
         }
@@ -593,7 +595,9 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_batched(
     static_assert(gs.per_group >= npairs, "batches need a single pair group");
     const int ti = find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x);
     const BatchGramTask tk = tasks[ti];
-    if (conditional && !(*tk.status & 4)) return;  // uniform over the workgroup
+    // uniform over the workgroup: 1 = the redo of uncertain ranks (bit 4),
+    // 2 = the problems marked FP64-only (bit 8)
+    if (conditional && !(*tk.status & (conditional == 2 ? 8 : 4))) return;
     const int w = blockIdx.x - tk.v.wg_begin;
     const TileMap tm = make_tiles(batch_mode_view(tk.v), gs.KT);
     const int active = (int)(tm.ntiles < tk.v.nwg ? tm.ntiles : tk.v.nwg);
@@ -615,6 +619,27 @@ static int launch_f64_batched_t(const BatchGramTask* tasks, int ntasks, int tota
                                (int)lds));
     hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kGramThreads), lds, st, tasks, ntasks,
                        conditional);
+    TK_HIP(hipGetLastError());
+    return TK_OK;
+}
+
+// One thread per task: the problem's FP64 Gram work at its actual shape
+// (the truncated extents come from the device ranks) decides bit 8.
+__global__ __launch_bounds__(64) void batch_mark_fp64(const BatchGramTask* __restrict__ tasks,
+                                                      int ntasks, double max_flops) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= ntasks) return;
+    const BatchGramTask tk = tasks[t];
+    const ModeView v = batch_mode_view(tk.v);
+    const double flops = 2.0 * (double)v.J * (double)v.J * (double)v.L * (double)v.B;
+    if (flops <= max_flops) *const_cast<int*>(tk.status) |= 8;  // the task is the word's only writer here
+}
+
+int launch_batch_mark_fp64(const BatchGramTask* tasks_dev, int ntasks, double max_flops,
+                           hipStream_t st) {
+    if (ntasks <= 0) return TK_OK;
+    hipLaunchKernelGGL(batch_mark_fp64, dim3((ntasks + 63) / 64), dim3(64), 0, st, tasks_dev,
+                       ntasks, max_flops);
     TK_HIP(hipGetLastError());
     return TK_OK;
 }

@@ -1078,6 +1078,7 @@ __global__ __launch_bounds__(kMxThreads) void gram_s16_batched(
     tk.partial = uni(tk.partial);
     tk.aux = uni(tk.aux);
     tk.tpw = uni(tk.tpw);
+    if (tk.status && (uni(*tk.status) & 8)) return;  // uniform: marked for the FP64 pass
     const int w = blockIdx.x - uni(tk.v.wg_begin);
     const ModeView mv = uni(batch_mode_view(tk.v));
     if (batch_loader(mv, tk.y) != MODE) return;  // uniform: another launch's task

@@ -377,7 +377,8 @@ struct BatchGramTask {
     const float* y;
     double* partial;     // nwg partial slots
     double* aux;         // nwg x 2 split statistics (split-bf16 Gram)
-    const int* status;   // the problem's status word (bit 4: rank not certified)
+    const int* status;   // the problem's status word (bit 4: rank not certified,
+                         // bit 8: FP64 Gram only)
     int* nparts;         // partial slots written by the last Gram launch
     int tpw;             // split-Gram tiles per workgroup
 };
@@ -401,10 +402,17 @@ struct BatchReduceTask {
 
 int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
                               hipStream_t st);
+// Sets status bit 8 of every task's problem whose FP64 Gram (2 K J^2 flops at
+// the actual shape) is at most max_flops: the split Gram skips it, the FP64
+// Gram launched with conditional = 2 takes it, and the reduction and the
+// eigensolver treat it as an FP64 Gram (the eigensolver clears the bit).
+int launch_batch_mark_fp64(const BatchGramTask* tasks_dev, int ntasks, double max_flops,
+                           hipStream_t st);
 int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
                             int kmax, int precision, hipStream_t st);
-// conditional != 0: only problems whose status has bit 4 set take part (the
-// guard's FP64 recomputation); the others' workgroups return at once.
+// conditional = 1: only problems whose status has bit 4 set take part (the
+// guard's FP64 recomputation), = 2: only those with bit 8 (FP64-only); the
+// others' workgroups return at once.
 int launch_gram_f64_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
                             int conditional, hipStream_t st);
 int launch_gram_reduce_batched(const BatchReduceTask* tasks_dev, int ntasks, int total_wg,
