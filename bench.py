@@ -145,6 +145,20 @@ def slab_check(x64, x32, eps):
     return cpu, out
 
 
+def profiled_json(stem):
+    """A committed profile record profiles/<stem>.json, or None when the
+    source it names has changed since it was taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", f"{stem}.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec if sha == rec["source_sha256"] else None
+
+
 def profiled(name):
     """The committed profile record of a kernel (profiles/traffic_<name>.json:
     HBM bytes per launch from FETCH_SIZE and WRITE_SIZE runs, scaled by a
@@ -196,9 +210,12 @@ def run_leg(name, x, w, gp, tp, steps, warmup):
         comp.run(x)
         log(f"[{name}] warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
+    gram_in_step = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        comp.run(x)
+        # the first mode's partial-Gram kernel, timed inside the step by the
+        # library with HIP events on its stream
+        gram_in_step.append(comp.run(x, time_first_gram=True))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt / steps * 1e3
@@ -216,6 +233,7 @@ def run_leg(name, x, w, gp, tp, steps, warmup):
            "relerr": math.sqrt(e2 / n2), "max_abs_err": mx, "gram": gp, "ttm": tp,
            "storage": str(x.dtype).replace("torch.", ""), "fp64_modes": list(res.fp64_modes),
            "ttm_precision_used": res.ttm_precision,
+           "mode1_gram_in_step_ms": round(sum(gram_in_step) / len(gram_in_step), 4),
            "tail_error_bound_over_tau": [b / (w.eps ** 2 * res.norm2 / len(w.dims)) if w.eps > 0
                                          else 0.0 for b in res.tail_error_bound]}
     log(f"[{name}] {steps} steps: {ms:.3f} ms/step, {leg['input_gbs']} GB/s, ranks {res.ranks},"
@@ -660,23 +678,34 @@ def main():
     x = x32 if head == "mixed" else x64
     leg, k = legs[head], kern[head]
     in_bytes = x.numel() * x.element_size()
+    # the dominant kernel's average launch time over the timed steps (HIP events
+    # recorded by the library around that launch on its stream); the same
+    # kernel launched back to back outside the steps is reported beside it
+    t_launch = leg["mode1_gram_in_step_ms"]
     if head == "mixed":
-        achieved = in_bytes / (k["gram_ms"] / 1e3) / 1e9
+        achieved = in_bytes / (t_launch / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic("gram_split_combustion128"),
                 "kernel": "gram_partial_s16 (mode 1, J=128, FP32 input, int8 matrix cores)",
-                "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": k["gram_ms"]}
+                "algorithmic_bytes_per_launch": in_bytes, "avg_launch_ms": t_launch,
+                "isolated_avg_launch_ms": k["gram_ms"]}
+        # the committed kernel traces' figures, beside this run's HIP events: the
+        # same launch inside the traced bench's timed steps, and back to back
         rec = profiled("gram_split_combustion128")
-        if rec:  # the committed kernel trace's figure, beside this run's HIP events
-            roof["profile_avg_launch_ms"] = rec.get("trace_avg_ms")
+        if rec:
+            roof["profile_isolated_avg_launch_ms"] = rec.get("trace_avg_ms")
+        rec = profiled_json("trace_gram_split_in_step")
+        if rec:
+            roof["profile_avg_launch_ms"] = rec.get("avg_ms")
     else:
         flops = gram_flops(w.dims[0], x.numel())
-        achieved = flops / (k["gram_ms"] / 1e3) / 1e12
+        achieved = flops / (t_launch / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFS, 4),
                 "traffic": None, "kernel": "gram_partial_f64 (mode 1, J=128)",
-                "algorithmic_flops_per_launch": flops, "avg_launch_ms": k["gram_ms"]}
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": t_launch,
+                "isolated_avg_launch_ms": k["gram_ms"]}
 
     out = {
         "metric": "ST-HOSVD input GB/s + Gram/TTM TFLOP/s, mixed vs FP64 GPU at rel err <=1e-4",

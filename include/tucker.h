@@ -229,6 +229,11 @@ typedef struct tk_options {
                                     workspace; a rank above it fails with TK_ERR_CAPACITY */
     int32_t gram_precision;      /* tk_gram_precision */
     int32_t ttm_precision;       /* tk_ttm_precision */
+    int32_t time_first_gram;     /* nonzero: sthosvd_compress brackets the first processed
+                                    mode's partial-Gram kernel with two HIP events on its
+                                    stream and reports their interval in
+                                    tk_tucker.first_gram_ms (a caller timing the dominant
+                                    kernel inside its pipeline); 0 = no events */
 } tk_options;
 
 typedef struct tk_tucker {
@@ -271,6 +276,10 @@ typedef struct tk_tucker {
                                           bound and falls short of the next larger tail sum
                                           by the same bound taken there; otherwise the mode
                                           is redone in FP64. */
+    double first_gram_ms;              /* with tk_options.time_first_gram: the interval, in
+                                          ms, between the HIP events recorded just before and
+                                          just after the first processed mode's partial-Gram
+                                          kernel; 0 otherwise */
 } tk_tucker;
 
 /*

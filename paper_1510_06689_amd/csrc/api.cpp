@@ -433,6 +433,19 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     double* lam_all = out->eigvals_dev ? out->eigvals_dev : lam_ws;
 
     TK_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(double), st));
+    // events around the first mode's partial Gram, destroyed on every return
+    struct GramEvents {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~GramEvents() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } gev;
+    out->first_gram_ms = 0.0;
+    if (opt->time_first_gram && !qr) {
+        TK_HIP(hipEventCreate(&gev.e[0]));
+        TK_HIP(hipEventCreate(&gev.e[1]));
+    }
 
     int64_t lam_off[TK_MAX_NDIM];
     {
@@ -469,7 +482,8 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
         } else {
             TK_TRY(launch_gram(ycur, x->dtype, v, gprec, S, s == 0 ? nu_dev : nullptr, gram_ws,
                                pl.gram_bytes, st,
-                               gprec == TK_GRAM_SPLIT_BF16 ? stats_dev : nullptr));
+                               gprec == TK_GRAM_SPLIT_BF16 ? stats_dev : nullptr,
+                               s == 0 && gev.e[0] ? gev.e : nullptr));
         }
         EigArgs ea;
         ea.s = S;
@@ -561,6 +575,11 @@ int sthosvd_compress(const tk_shape* x, const void* x_dev, const tk_options* opt
     out->norm2 = nu_host;
     out->fp64_modes = fp64_modes;
     out->ttm_precision_used = ttm_prec;
+    if (gev.e[0]) {  // both recorded before the synchronisation above
+        float ms = 0.0f;
+        TK_HIP(hipEventElapsedTime(&ms, gev.e[0], gev.e[1]));
+        out->first_gram_ms = ms;
+    }
     return TK_OK;
 }
 

@@ -656,13 +656,14 @@ int launch_gram_f64_batched(const BatchGramTask* tasks_dev, int ntasks, int tota
 
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
                 double* sumsq, void* ws, size_t ws_bytes, hipStream_t st,
-                double* split_stats) {
+                double* split_stats, const hipEvent_t* ev) {
     GramPlan pl = plan_gram(v, precision, (int)dtype_size(dtype));
     if (ws_bytes < pl.partial_bytes)
         return fail(TK_ERR_WORKSPACE, "gram workspace %zu < %zu", ws_bytes, pl.partial_bytes);
     double* partial = (double*)ws;
     // the narrow kernel's 8-element vector loads need the run's own alignment
     if (pl.narrow && (uintptr_t)y % (8 * dtype_size(dtype)) != 0) pl = plan_tiled(v);
+    if (ev) TK_HIP(hipEventRecord(ev[0], st));
     if (precision == TK_GRAM_SPLIT_BF16) {
         TK_TRY(launch_gram_mixed((const float*)y, v, pl, partial, st));
     } else if (pl.narrow) {
@@ -675,6 +676,7 @@ int launch_gram(const void* y, int dtype, const ModeView& v, int precision, doub
     } else {
         TK_TRY(dispatch_partial((const float*)y, v, pl, partial, st));
     }
+    if (ev) TK_HIP(hipEventRecord(ev[1], st));
     const bool split = precision == TK_GRAM_SPLIT_BF16;
     const double* aux = split && split_stats ? partial + (size_t)pl.P * pl.npairs * 256 : nullptr;
     TK_TRY(launch_gram_reduce(partial, pl, v.J, s, aux, split_stats, st));

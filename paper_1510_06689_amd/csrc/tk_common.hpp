@@ -165,9 +165,11 @@ int launch_gram_mixed(const float* y, const ModeView& v, const GramPlan& pl, dou
                       hipStream_t st);
 // split_stats (may be NULL; split-bf16 Grams only): receives {sum of d^2,
 // largest row exponent} of the split representation (see EigArgs).
+// ev: NULL, or two events recorded on st just before and just after the
+// partial-Gram kernel (not the reduction).
 int launch_gram(const void* y, int dtype, const ModeView& v, int precision, double* s,
                 double* sumsq, void* ws, size_t ws_bytes, hipStream_t st,
-                double* split_stats = nullptr);
+                double* split_stats = nullptr, const hipEvent_t* ev = nullptr);
 
 int launch_ttm(const void* y, int dtype, const ModeView& v, const double* m, int64_t K,
                int64_t ldm, int transpose, int precision, void* z, hipStream_t st);

@@ -59,7 +59,8 @@ class Options(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("mode_order", ctypes.POINTER(ctypes.c_int32)),
                 ("fixed_ranks", ctypes.POINTER(ctypes.c_int64)),
                 ("max_ranks", ctypes.POINTER(ctypes.c_int64)),
-                ("gram_precision", ctypes.c_int32), ("ttm_precision", ctypes.c_int32)]
+                ("gram_precision", ctypes.c_int32), ("ttm_precision", ctypes.c_int32),
+                ("time_first_gram", ctypes.c_int32)]
 
 
 class Tucker(ctypes.Structure):
@@ -68,7 +69,8 @@ class Tucker(ctypes.Structure):
                 ("ranks", ctypes.c_int64 * MAX_NDIM), ("discarded", ctypes.c_double * MAX_NDIM),
                 ("norm2", ctypes.c_double), ("fp64_modes", ctypes.c_uint32),
                 ("ttm_precision_used", ctypes.c_int32),
-                ("tail_error_bound", ctypes.c_double * MAX_NDIM)]
+                ("tail_error_bound", ctypes.c_double * MAX_NDIM),
+                ("first_gram_ms", ctypes.c_double)]
 
 
 class BatchOutputs(ctypes.Structure):
@@ -366,15 +368,20 @@ class Compressor:
             self.out.factors_dev[k] = f.data_ptr()
         self.out.eigvals_dev = self.eig_buf.data_ptr()
 
-    def run(self, x: torch.Tensor) -> None:
-        """One ST-HOSVD of ``x``; synchronises the current stream."""
+    def run(self, x: torch.Tensor, time_first_gram: bool = False) -> float:
+        """One ST-HOSVD of ``x``; synchronises the current stream.  With
+        ``time_first_gram`` returns the duration (ms) of the first processed
+        mode's partial-Gram kernel, timed with HIP events inside the call;
+        else 0."""
         if tuple(x.shape) != self.dims or x.dtype != self.dtype:
             raise ValueError("tensor does not match the compressor's shape/dtype")
         _require_device(x)
+        self.opt.time_first_gram = 1 if time_first_gram else 0
         _check(library().sthosvd_compress(ctypes.byref(self.shape), x.data_ptr(),
                                           ctypes.byref(self.opt), ctypes.byref(self.out),
                                           _aligned(self.ws), self.ws_bytes,
                                           _stream(self.device)))
+        return float(self.out.first_gram_ms)
 
     def run_hooi(self, x: torch.Tensor, max_sweeps: int = 20, tol: float = 0.0) -> list:
         """Alg. 2 (HOOI) of ``x`` from this compressor's ST-HOSVD settings;

@@ -321,3 +321,25 @@ def test_mixed_bf16_ttm_raised_under_eps_rule(eps, expect):
     fixed = tucker.sthosvd(to_dev(x), 0.0, ranks=ref.ranks, gram_precision="split_bf16",
                            ttm_precision="bf16")
     assert fixed.ttm_precision == "bf16"        # fixed ranks keep the request
+
+
+def test_first_gram_timing_leaves_results_unchanged():
+    """tk_options.time_first_gram: the call reports a positive duration for
+    the first mode's partial-Gram kernel (HIP events inside the call) and
+    otherwise computes exactly what the untimed call computes."""
+    x = synth.planted_tucker((96, 40, 36, 8), (8, 6, 6, 3), rho=0.7, factor_kind="cosine",
+                             noise=1e-5, noise_mode="sigma", seed=81, dtype=torch.float32)
+    xd = to_dev(x)
+    for gp, tp in (("split_bf16", "bf16x3"), ("fp64", "fp64")):
+        c = tucker.Compressor(x.shape, x.dtype, xd.device, 1e-4, gram_precision=gp,
+                              ttm_precision=tp)
+        assert c.run(xd) == 0.0
+        r0 = c.result(copy=True)
+        t = c.run(xd, time_first_gram=True)
+        r1 = c.result(copy=True)
+        say(f"{gp}/{tp}: first-mode partial Gram {t:.4f} ms, ranks {r1.ranks}")
+        assert 0.0 < t < 1e3
+        assert r0.ranks == r1.ranks
+        assert torch.equal(r0.core, r1.core)
+        assert all(torch.equal(a, b) for a, b in zip(r0.factors, r1.factors))
+        assert c.run(xd) == 0.0  # the flag is per call
