@@ -41,6 +41,14 @@ struct GramLaunch {
 // costs no more than the split Gram, and its rank needs no guard.
 bool f64_class(int jb) { return jb <= 32; }
 
+// Workgroups of one problem's Gram: its tiles over tiles-per-workgroup.  An
+// FP64 class's problems are small and its kernel walks finer tiles, so it
+// takes a quarter of the tiles per workgroup (more workgroups in flight).
+int gram_wgs(int64_t ntiles, int tpw, int jb) {
+    const int t = f64_class(jb) ? std::max(1, tpw / 4) : tpw;
+    return std::max(1, std::min(4096, (int)((ntiles + t - 1) / t)));
+}
+
 // From the second step on, a problem of a split class whose FP64 Gram takes
 // at most this many flops (2 K J^2 at its actual shape, known on the device
 // only) is marked before the Grams (status bit 8) and takes the FP64 Gram
@@ -182,7 +190,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int nb16 = 2 * (jb / 32), np16 = nb16 * (nb16 + 1) / 2;
             const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
                                                                : kDefaultGramTilesPerWg;
-            const int nwg = std::max(1, std::min(4096, ceil_div(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw)));
+            const int nwg = gram_wgs(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw, jb);
             pb = std::max(pb, (size_t)nwg * np16 * 256 * sizeof(double));
             ab = std::max(ab, (size_t)nwg * 2 * sizeof(double));
             jmax = std::max(jmax, v.J);
@@ -237,7 +245,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
                                                                : kDefaultGramTilesPerWg;
             const int64_t ntiles = make_tiles(v, mx_gram_kt(jb)).ntiles;
-            const int nwg = std::max(1, std::min(4096, ceil_div(ntiles, tpw)));
+            const int nwg = gram_wgs(ntiles, tpw, jb);
             BatchView bv{};
             for (int k = 0; k < N; ++k) bv.dims[k] = sh.dims[k];
             bv.ranks = h ? h->ranks_dev + (size_t)b * N : nullptr;
