@@ -121,7 +121,9 @@ struct SplitTile {
     unsigned okm[NBUF];       // kUnit4: bit 8 s + e set if set s, element e is inside the tile
     int i0, cg0;
     bool owner;      // kUnit: this wave holds rows
-    int coff[8];     // strided: offsets of the thread's 8 columns inside a tile
+    // Offsets of the thread's 8 columns inside a tile.  kContig (L % 8 == 0)
+    // keeps coff[0] only: the 8 columns lie in one run of L, at coff[0] + e.
+    int coff[8];
     // Representation error of the split: per row of the thread, the sum of
     // d^2 over its elements, d = x - 2^(E-7) (hi + lo) exactly, and the
     // largest row exponent E it used.
@@ -153,7 +155,8 @@ struct SplitTile {
             cg0 = tid % NCG;
             i0 = tid / NCG;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) coff[e] = (int)col_offset(8 * cg0 + e, tm.L, tm.J);
+            for (int e = 0; e < (MODE == kContig ? 1 : 8); ++e)
+                coff[e] = (int)col_offset(8 * cg0 + e, tm.L, tm.J);
         }
     }
     __device__ __forceinline__ int row_of(int m) const {
@@ -187,6 +190,36 @@ struct SplitTile {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) v[4 * st + j][e] = x[j];
             }
+    }
+
+    // kContig, full tile (KT columns, J == JB): the elements load() reads,
+    // as raw buffer loads with no test around them.  The tile's base goes into
+    // a scalar descriptor whose range is the tile, the lane's offset (row i0,
+    // column 8 cg0) is fixed and the row step is a scalar offset, so no vector
+    // register is written to address the loads.  The caller guarantees that
+    // a tile spans fewer than 2^31 bytes.
+    template <int B>
+    __device__ __forceinline__ void load_full_contig(const float* __restrict__ y,
+                                                     const TileMap& tm, const Tile& t) {
+        static_assert(MODE == kContig, "contiguous full-tile loads");
+        float(&v)[NGRP][8] = vb[B];
+        const int L4 = (int)tm.L * (int)sizeof(float);
+        const int range =
+            (JB - 1) * L4 + ((int)col_offset(KT - 1, tm.L, JB) + 1) * (int)sizeof(float);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)uni(y + t.base), (short)0, range, 0x00020000);  // as in load_full
+        const int voff = (i0 * (int)tm.L + coff[0]) * (int)sizeof(float);
+#pragma unroll
+        for (int m = 0; m < NGRP; ++m) {
+            const int so = m * ROWSTEP * L4;
+            const f4_t a = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so, 0);
+            const f4_t b = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so + 16, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[m][e] = a[e];
+                v[m][4 + e] = b[e];
+            }
+        }
     }
 
     template <int B = 0>
@@ -258,7 +291,8 @@ struct SplitTile {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int kk = 8 * cg0 + e;
-                        v[m][e] = (i < J && kk < t.ncols) ? y[rowbase + coff[e]] : 0.f;
+                        const int ce = MODE == kContig ? coff[0] + e : coff[e];
+                        v[m][e] = (i < J && kk < t.ncols) ? y[rowbase + ce] : 0.f;
                     }
                 }
             }
@@ -859,30 +893,38 @@ __device__ __forceinline__ void gram_s16_body(
             __syncthreads();
         }
     } else {
-        // Two register tiles; only for kUnit4 with J == JB, where every tile
-        // but the tensor's last is full.  The loop runs over the full tiles
-        // [t0, tf) with loads clamped to tf - 1 and no branch around them; a
-        // ragged last tile follows on its own.
-        static_assert(NBUF == 2 && MODE == kUnit4, "two register tiles: kUnit4 only");
+        // Two register tiles; only for kUnit4 or kContig with J == JB, where
+        // every tile but the tensor's last is full.  The loop runs over the
+        // full tiles [t0, tf) with loads clamped to tf - 1 and no branch around
+        // them; a ragged last tile follows on its own.
+        static_assert(NBUF == 2 && (MODE == kUnit4 || MODE == kContig),
+                      "two register tiles: kUnit4 or kContig");
+        auto load_full = [&](auto bc, int64_t tt) {
+            constexpr int BB = decltype(bc)::value;
+            if constexpr (MODE == kUnit4)
+                ld.template load_full<BB>(y, tt);
+            else
+                ld.template load_full_contig<BB>(y, tm, tile_at(tm, tt, tm.J));
+        };
         // tile counters relative to t0 in 32 bits (a workgroup's range is far
         // below 2^31 tiles), so that every comparison stays scalar
         int nf = (int)(t1 - t0);
         if (nf > 0 && tile_at(tm, t1 - 1, tm.J).ncols < KT) --nf;
         auto tile = [&](int r) { return t0 + (r < nf ? r : nf - 1); };
         if (nf > 0) {  // uniform
-            ld.template load_full<0>(y, tile(0));
+            load_full(std::integral_constant<int, 0>{}, tile(0));
             ld.template store16<0>(hi_of(0), hi_of(0) + PLANE, sc_of(0));
-            ld.template load_full<1>(y, tile(1));
+            load_full(std::integral_constant<int, 1>{}, tile(1));
             __syncthreads();
             int r = 0;
             for (;;) {
                 // LDS buffer 0: tile r; registers 1: tile r + 1 (loaded)
-                ld.template load_full<0>(y, tile(r + 2));
+                load_full(std::integral_constant<int, 0>{}, tile(r + 2));
                 mfma_tile(0);
                 ld.template store16<1>(hi_of(1), hi_of(1) + PLANE, sc_of(1), r + 1 < nf);
                 __syncthreads();
                 if (++r >= nf) break;
-                ld.template load_full<1>(y, tile(r + 2));
+                load_full(std::integral_constant<int, 1>{}, tile(r + 2));
                 mfma_tile(1);
                 ld.template store16<0>(hi_of(0), hi_of(0) + PLANE, sc_of(0), r + 1 < nf);
                 __syncthreads();
@@ -1053,6 +1095,16 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
     }
     if (v.L == 1) return mx_launch<JB, kUnit>(y, tm, pl, partial, st);
     const bool contig = v.L % 8 == 0 && ((uintptr_t)y & 15) == 0;
+    if constexpr (JB == 128) {
+        // two register tiles: J == JB, every tile but the tensor's last full
+        // (KT a multiple of L when tiles pack whole b-blocks, L a multiple of
+        // KT when they cut one), and a full tile spans < 2^31 bytes
+        const int64_t kl = pl.KT - 1;
+        const int64_t span = (int64_t)(v.J - 1) * v.L + (kl / v.L) * v.J * v.L + kl % v.L + 1;
+        const bool even = tm.packed ? pl.KT % v.L == 0 : v.L % pl.KT == 0;
+        if (contig && v.J == JB && even && span * (int64_t)sizeof(float) < (int64_t(1) << 31))
+            return mx_launch<JB, kContig, 2>(y, tm, pl, partial, st);
+    }
     if (contig) return mx_launch<JB, kContig>(y, tm, pl, partial, st);
     return mx_launch<JB, kStrided>(y, tm, pl, partial, st);
 }

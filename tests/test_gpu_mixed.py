@@ -62,6 +62,12 @@ GRAM_CASES = [
     ((100, 9, 13), (0,)),       # J % 4 == 0 with L == 1: 16-byte column pieces, J class 128
     ((132, 5, 7), (0,)),        # the same for J class 256 (three pair groups)
     ((128, 1000), (0,)),        # several tiles per workgroup and a ragged last tile
+    # J == 128 with L % 8 == 0: two register tiles where tile widths divide
+    ((8, 128, 700), (1,)),      # 16 b-blocks per tile, ragged last tile
+    ((16, 128, 45), (1,)),      # 8 b-blocks per tile, ragged last tile
+    ((256, 128, 5), (1,)),      # each b-block cut into two full tiles
+    ((24, 128, 20), (1,)),      # 128 % 24 != 0: one register tile
+    ((200, 128, 3), (1,)),      # 200 % 128 != 0: one register tile
 ]
 
 
