@@ -157,13 +157,13 @@ size_t gram_workspace_bytes(const tk_shape* y, int mode, int precision);
  * memory (code under graph capture, tight serving loops, harnesses that
  * forbid allocation).  Same arguments, kernels and results as gram_mode_n;
  * the scratch (Gram partials and split statistics) is a static device array
- * of gram_noalloc_scratch_bytes() bytes (64 MiB), one per device, allocated
+ * of gram_noalloc_scratch_bytes() bytes (72 MiB), one per device, allocated
  * with the library's code on that device and held until the process ends.
  * Shapes whose gram_workspace_bytes exceed it fail with TK_ERR_WORKSPACE;
  * no shape the library accepts does (the Gram's grid is capped per extent,
- * so its partials do not grow with the other modes: the largest, J = 337 in
- * FP64, needs 63.3 MiB).  Argument errors as gram_mode_n, reported before
- * any device call.  The call allocates nothing
+ * so its partials do not grow with the other modes: the largest, the split
+ * Gram of J in 129..256 with L = 1, needs 68.0 MiB).  Argument errors as
+ * gram_mode_n, reported before any device call.  The call allocates nothing
  * (no hipMalloc, no library allocation).  Every call on a device shares that
  * device's array: calls that overlap on one device (other streams, other
  * threads) race and must be serialised by the caller.

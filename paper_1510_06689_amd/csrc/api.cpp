@@ -161,7 +161,7 @@ int gram_mode_n(const tk_shape* y, const void* y_dev, int mode, int precision, d
 // never uses the array's name as an address: each device's copy is looked up
 // once (hipGetSymbolAddress with that device current) and that pointer is what
 // the kernels receive.
-constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoAllocScratchBytes = (size_t)72 << 20;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {

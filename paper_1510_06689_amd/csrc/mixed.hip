@@ -247,11 +247,15 @@ struct SplitTile {
                 const bool rok = i0 < J;
                 const int ic = rok ? i0 : J - 4;
                 unsigned mk = 0;
+                // opaque here, so that the column indices below are formed
+                // per call rather than held across the tile loop
+                int c0 = cg0;
+                asm volatile("" : "+v"(c0));
 #pragma unroll
                 for (int st = 0; st < NSET; ++st)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int kk = 8 * (cg0 + CGW * st) + e;
+                        const int kk = 8 * (c0 + CGW * st) + e;
                         mk |= (rok && kk < t.ncols) ? 1u << (8 * st + e) : 0u;
                         const int kc = kk < t.ncols ? kk : t.ncols - 1;
                         const f4_t x = *(const f4_t*)(y + t.base + (int64_t)kc * J + ic);
@@ -778,8 +782,9 @@ __device__ __forceinline__ void gram_s16_body(
             act[q] = pl < pairs_per_group && p < npairs16;
             pair32_of(act[q] ? p : 0, NB, bi[q], bj[q]);  // the upper-triangle order, NB blocks
         }
-        aoff[q] = (16 * bi[q] + r16) * PKB + 16 * kq;
-        boff[q] = (16 * bj[q] + r16) * PKB + 16 * kq;
+        // block parts only (wave-uniform); the lane part is added per tile
+        aoff[q] = 16 * bi[q] * PKB;
+        boff[q] = 16 * bj[q] * PKB;
     }
 
     double accd[NPW][4];
@@ -854,16 +859,21 @@ __device__ __forceinline__ void gram_s16_body(
             }
             return;
         }
+        // lane part of the fragment offsets, opaque here so that its sums
+        // with the pairs' block parts are formed per tile, not held across
+        // the loop in a register per pair
+        int lo = r16 * PKB + 16 * kq;
+        asm volatile("" : "+v"(lo));
 #pragma unroll
         for (int q = 0; q < NPW; ++q) {
             if (!act[q]) continue;
             i4v_t hh = {0, 0, 0, 0}, mm = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
-                const i4v_t ah = *(const i4v_t*)(hb + aoff[q] + 64 * ks);
-                const i4v_t al = *(const i4v_t*)(lb + aoff[q] + 64 * ks);
-                const i4v_t bh = *(const i4v_t*)(hb + boff[q] + 64 * ks);
-                const i4v_t bl = *(const i4v_t*)(lb + boff[q] + 64 * ks);
+                const i4v_t ah = *(const i4v_t*)(hb + lo + aoff[q] + 64 * ks);
+                const i4v_t al = *(const i4v_t*)(lb + lo + aoff[q] + 64 * ks);
+                const i4v_t bh = *(const i4v_t*)(hb + lo + boff[q] + 64 * ks);
+                const i4v_t bl = *(const i4v_t*)(lb + lo + boff[q] + 64 * ks);
                 hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bh, hh, 0, 0, 0);
                 mm = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, bl, mm, 0, 0, 0);
                 mm = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, bh, mm, 0, 0, 0);
@@ -992,7 +1002,7 @@ __global__ __launch_bounds__(kMxThreads) void gram_partial_bf16s(
 }
 
 // Static schedule per padded extent: tile width, pairs per wave, pair groups
-// (each re-reads the tensor), workgroups per CU.  Extents up to 256 run the
+// (each streams and splits every tile again), workgroups per CU.  Extents up to 256 run the
 // int8 kernel on 16-block pairs, 512 the bf16 kernel on 32-block pairs.
 struct MxGramShape {
     int KT, NPW, G, per_cu, NW;  // NW: waves per workgroup
@@ -1001,9 +1011,11 @@ template <int JB>
 constexpr bool mx_int8() {
     return JB <= 256;
 }
-// UNIT: the view has L == 1.  At extent 256 its loaders leave room for 9
-// pairs per wave (two pair groups of 68: every tile split twice), the
-// strided loaders for 6 (three groups of 46).  A pair's int32 sums live only
+// UNIT: the view has L == 1.  At extent 256 its loaders (one register tile)
+// leave room for 17 pairs per wave: one pair group of 136 on tiles of 128
+// columns, so every tile is split once and the FP64 flushes come once per
+// 128 columns; the strided loaders leave room for 6 (three groups of 46 on
+// tiles of 64).  A pair's int32 sums live only
 // from its first MFMA to its flush; the FP64 accumulators of all the wave's
 // pairs (8 registers each) are what limits the count.
 template <int JB, bool UNIT = false>
@@ -1011,7 +1023,7 @@ constexpr MxGramShape mx_gram_shape() {
     return JB == 32    ? MxGramShape{128, 1, 1, 2, 8}    //   3 16-pairs
            : JB == 64  ? MxGramShape{128, 2, 1, 2, 8}    //  10 16-pairs
            : JB == 128 ? MxGramShape{128, 5, 1, 1, 8}    //  36 16-pairs, 9 per SIMD
-           : JB == 256 ? (UNIT ? MxGramShape{64, 9, 2, 1, 8}     // 136 16-pairs: 2 x 68
+           : JB == 256 ? (UNIT ? MxGramShape{128, 17, 1, 1, 8}   // 136 16-pairs: 1 x 136
                                : MxGramShape{64, 6, 3, 1, 8})    //               3 x 46
                        : MxGramShape{16, 2, 9, 1, 8};    // 136 32-pairs: 9 groups of 16
 }
@@ -1088,10 +1100,14 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
                             double* partial, hipStream_t st) {
     TileMap tm = make_tiles(v, pl.KT);
     if constexpr (JB == 128 || JB == 256) {
-        if (v.L == 1 && v.J % 4 == 0 && ((uintptr_t)y & 15) == 0)
-            // two register tiles (J == JB only)
-            return v.J == JB ? mx_launch<JB, kUnit4, 2>(y, tm, pl, partial, st)
-                             : mx_launch<JB, kUnit4, 1>(y, tm, pl, partial, st);
+        if (v.L == 1 && v.J % 4 == 0 && ((uintptr_t)y & 15) == 0) {
+            // two register tiles at extent 128 with J == JB; extent 256 keeps
+            // one (its 17 pairs per wave take the registers of the second)
+            if constexpr (JB == 128) {
+                if (v.J == JB) return mx_launch<JB, kUnit4, 2>(y, tm, pl, partial, st);
+            }
+            return mx_launch<JB, kUnit4, 1>(y, tm, pl, partial, st);
+        }
     }
     if (v.L == 1) return mx_launch<JB, kUnit>(y, tm, pl, partial, st);
     const bool contig = v.L % 8 == 0 && ((uintptr_t)y & 15) == 0;

@@ -112,7 +112,9 @@ def test_batch_guard_recomputes_on_device():
         c.run()
         torch.cuda.synchronize()
         status = c.status_dev.view(-1, 2).cpu().numpy()
-        assert not (status[:, 0] & 4).any(), status
+        # no uncertain rank (4) left, and no FP64-only mark (8) of a later
+        # step's small problem outlives its eigensolver pass
+        assert not (status[:, 0] & 12).any(), status
         c.finish()
         res = c.results()
         if batch is not xs:
