@@ -1142,9 +1142,9 @@ __global__ __launch_bounds__(kMxThreads) void gram_s16_batched(
     constexpr MxGramShape gs = mx_gram_shape<JB>();
     const int ti = uni(find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x));
     BatchGramTask tk = tasks[ti];
-    tk.y = uni(tk.y);
-    tk.partial = uni(tk.partial);
-    tk.aux = uni(tk.aux);
+    tk.y = uni_global(tk.y);
+    tk.partial = uni_global(tk.partial);
+    tk.aux = uni_global(tk.aux);
     tk.tpw = uni(tk.tpw);
     if (tk.status && (uni(*tk.status) & 8)) return;  // uniform: marked for the FP64 pass
     const int w = blockIdx.x - uni(tk.v.wg_begin);
@@ -1219,7 +1219,11 @@ constexpr int kMtWaves = kMtThreads / 64;
 
 // NKB: 16-row blocks of op(M) per workgroup; NKS: 32-wide k-steps over J;
 // X3: split both operands (three products) instead of one bf16 product.
-// UNIT: columns contiguous (L == 1, J % 8 == 0), loaded as 16-byte vectors.
+// UNIT: L == 1, each column's J floats contiguous: a lane's 8 rows of a
+// column come in two 16-byte loads, and its 4 outputs go out in one 16-byte
+// store.  With J (or K) not a multiple of 4 these addresses are only 4-byte
+// aligned; the target runs in unaligned-access mode, where wide accesses at
+// any dword address are legal (memcpy lets the compiler emit them).
 // SKIP: row blocks at or beyond K skip their products (a batch sizes NKB for
 // the rank capacity, the rank comes later from the device).
 // The body stages rows [r0, r0 + 16 NKB) of op(M) and walks column blocks
@@ -1275,17 +1279,11 @@ __device__ __forceinline__ void ttm_bf16_body(
             const int j0 = 32 * ks + 8 * g4;
             float x[8];
             if (UNIT) {
-                if (cv && j0 < J) {
-                    const f4_t* p = (const f4_t*)(ycol + j0);
-                    const f4_t a = p[0], c = p[1];
+                if (cv && j0 + 8 <= J) {
+                    __builtin_memcpy(x, ycol + j0, sizeof(x));
+                } else {  // the column's last rows (J % 8 != 0), or no column
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        x[e] = a[e];
-                        x[4 + e] = c[e];
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) x[e] = 0.f;
+                    for (int e = 0; e < 8; ++e) x[e] = (cv && j0 + e < J) ? ycol[j0 + e] : 0.f;
                 }
             } else {
 #pragma unroll
@@ -1320,8 +1318,8 @@ __device__ __forceinline__ void ttm_bf16_body(
             const int rb = r0 + 16 * kb + 4 * g4;
             if (UNIT) {
                 float* zc = z + col * K;
-                if (rb + 4 <= K && (K & 3) == 0) {
-                    *(f4_t*)(zc + rb) = acc[kb];
+                if (rb + 4 <= K) {
+                    __builtin_memcpy(zc + rb, &acc[kb], sizeof(f4_t));
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
@@ -1350,8 +1348,7 @@ template <int NKB, int NKS, bool X3>
 static int mt_launch(const float* y, const ModeView& v, const double* m, int64_t ldm, int K,
                      int transpose, float* z, hipStream_t st) {
     const int64_t ncols = v.L * v.B;
-    const bool unit = v.L == 1 && v.J % 8 == 0 && ((uintptr_t)y & 15) == 0 &&
-                      ((uintptr_t)z & 15) == 0;
+    const bool unit = v.L == 1;
     const int G = (K + NKB * 16 - 1) / (NKB * 16);
     auto fn = unit ? ttm_bf16_kernel<NKB, NKS, X3, true> : ttm_bf16_kernel<NKB, NKS, X3, false>;
     int per_cu = 1;
@@ -1400,15 +1397,17 @@ __global__ __launch_bounds__(kMtThreads) void ttm_bf16_batched(const BatchTtmTas
                                                              int ntasks) {
     __shared__ bf8_t afr[NKB * NKS * 2][64];
     const int ti = find_task_wg(&tasks[0].v, sizeof(BatchTtmTask), ntasks, blockIdx.x);
-    const BatchTtmTask tk = tasks[ti];
+    BatchTtmTask tk = tasks[ti];
+    tk.y = uni_global(tk.y);
+    tk.u = uni_global(tk.u);
+    tk.z = uni_global(tk.z);
     const int w = blockIdx.x - tk.v.wg_begin;
     const ModeView mv = batch_mode_view(tk.v);
     const int K = (int)tk.v.ranks[tk.v.n];  // this mode's rank, decided on the device
     const int r0 = blockIdx.y * NKB * 16;
     if (r0 >= K) return;                     // row groups beyond the rank: nothing to do
     const int64_t ncols = mv.L * mv.B;
-    const bool unit = mv.L == 1 && mv.J % 8 == 0 && ((uintptr_t)tk.y & 15) == 0 &&
-                      ((uintptr_t)tk.z & 15) == 0;
+    const bool unit = mv.L == 1;
     if (unit)
         ttm_bf16_body<NKB, NKS, X3, true, true>(tk.y, mv.L, ncols, mv.J, tk.u, mv.J, K, 1, tk.z,
                                                 r0, w, tk.v.nwg, afr);

@@ -349,6 +349,17 @@ template <typename T>
 __device__ __forceinline__ T* uni(T* p) {
     return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
 }
+// A wave-uniform pointer to device global memory, typed so: it passes
+// through an empty asm as an integer, so the compiler cannot fold the casts
+// away, and every access derived from it becomes a global (not flat) load or
+// store.  A flat access also counts against the LDS counter, so that LDS
+// reads issued behind it would wait for it as well.
+template <typename T>
+__device__ __forceinline__ T* uni_global(T* p) {
+    uint64_t a = (uint64_t)(uintptr_t)uni(p);
+    asm volatile("" : "+s"(a));
+    return (T*)(__attribute__((address_space(1))) T*)a;
+}
 __device__ __forceinline__ ModeView uni(const ModeView& v) {
     ModeView u;
     u.L = uni(v.L);

@@ -122,6 +122,8 @@ TTM_CASES = [
     ((2, 200, 5), 1, 300), ((16, 300, 3), 1, 33), ((7,), 0, 3), ((512, 3), 0, 20),
     ((20, 30, 2), 2, 300), ((64, 9, 18), 0, 64), ((256, 40, 3), 0, 32),
     ((47, 32, 32, 16), 1, 23), ((47, 23, 32, 16), 2, 17),
+    # L == 1 with J % 8 != 0 and K % 4 != 0: 16-byte accesses at 4-byte alignment
+    ((37, 20, 11), 0, 5), ((100, 30, 7), 0, 12), ((93, 17, 5), 0, 33),
 ]
 
 
