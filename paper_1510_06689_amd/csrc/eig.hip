@@ -1292,7 +1292,7 @@ __global__ __launch_bounds__(64) void eig_multisect_batched(const EigArgs* __res
     if (kBatchGroups * q >= J) return;  // uniform over the workgroup
     if (conditional && !(args[p].flags[0] & 4)) return;  // the redo pass: bit 4 only
     const int k = kBatchGroups * q + (int)threadIdx.x / kBatchTpe;
-    multisect_group<kBatchTpe>(eig_handoff(args[p].scratch, J), J, k, k < J, sm);
+    multisect_group<kBatchTpe>(eig_handoff(uni_global(args[p].scratch), J), J, k, k < J, sm);
 }
 
 // One workgroup per problem of a batch, as PH = 1, eig_multisect_batched,
@@ -1306,6 +1306,17 @@ __global__ __launch_bounds__(kEigThreads) void eig_batched(const EigArgs* __rest
                                                            int region, int conditional,
                                                            int mode_bit) {
     EigArgs a = args[blockIdx.x];
+    // table pointers as global ones (global, not flat, accesses)
+    a.s = uni_global(a.s);
+    a.nu = uni_global(a.nu);
+    a.lambda = uni_global(a.lambda);
+    a.u = uni_global(a.u);
+    a.rank_out = uni_global(a.rank_out);
+    a.disc_out = uni_global(a.disc_out);
+    a.flags = uni_global(a.flags);
+    a.scratch = uni_global(a.scratch);
+    a.split_stats = uni_global(a.split_stats);
+    a.tail_bound = uni_global(a.tail_bound);
     const int f0 = a.flags ? a.flags[0] : 0;
     if (conditional && !(f0 & 4)) return;  // uniform over the workgroup
     if (conditional || (f0 & 8)) {

@@ -508,7 +508,9 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
         const int mid = (lo + hi + 1) >> 1;
         if (tasks[mid].wg_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
-    const BatchReduceTask tk = tasks[lo];
+    BatchReduceTask tk = tasks[lo];
+    tk.partial = uni_global(tk.partial);  // global, not flat, accesses
+    tk.s = uni_global(tk.s);
     if (conditional && !(*tk.status & 4)) return;  // uniform over the workgroup
     const int w = blockIdx.x - tk.wg_begin;
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -594,7 +596,9 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_batched(
     constexpr int nb = JB / 16, npairs = nb * (nb + 1) / 2;
     static_assert(gs.per_group >= npairs, "batches need a single pair group");
     const int ti = find_task_wg(&tasks[0].v, sizeof(BatchGramTask), ntasks, blockIdx.x);
-    const BatchGramTask tk = tasks[ti];
+    BatchGramTask tk = tasks[ti];
+    tk.y = uni_global(tk.y);  // global, not flat, accesses
+    tk.partial = uni_global(tk.partial);
     // uniform over the workgroup: 1 = the redo of uncertain ranks (bit 4),
     // 2 = the problems marked FP64-only (bit 8)
     if (conditional && !(*tk.status & (conditional == 2 ? 8 : 4))) return;
