@@ -359,8 +359,8 @@ def profile_kernels(w, dev, stream):
     and 3x the mode-1 split TTM (R = 16) of combustion128 stored FP32, 3x a
     plain copy of that tensor (whose byte counts calibrate FETCH_SIZE and
     WRITE_SIZE), 3x the split Gram of extent 256 (mode 1 of a 256^4 FP32
-    tensor: three pair groups) and 3x the mode-1 FP64 Gram of combustion128
-    stored FP64."""
+    tensor: one pair group on tiles of 128 columns) and 3x the mode-1 FP64
+    Gram of combustion128 stored FP64."""
     x = w.make(dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     res = tucker.sthosvd(x, w.eps, gram_precision="split_bf16", ttm_precision="bf16x3")
