@@ -764,6 +764,12 @@ __device__ __forceinline__ void gram_s16_body(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // pair choices stay scalar
     const int r16 = lane & 15, kq = lane >> 4;
     const int g0 = group * pairs_per_group;
+    // row blocks holding rows < J: a pair with a block past them sums zeros
+    // only, so it skips its products and flushes (its partial stays zero).
+    // Extents up to 128 (the batches' classes) with one register tile only:
+    // two register tiles run with J == JB, where no pair is skipped.
+    constexpr bool kSkip = NBUF == 1 && JB <= 128;
+    const int nbv = kSkip ? uni((tm.J + 15) >> 4) : NB;
 
     constexpr bool kSched = JB == 128 && NW == 8;  // the fixed per-wave schedule above
     static_assert(!kSched || NPW == 5, "the extent-128 schedule has up to 5 pairs per wave");
@@ -830,6 +836,7 @@ __device__ __forceinline__ void gram_s16_body(
 #pragma unroll
             for (int q = 0; q < ws.npair; ++q) {
                 const int a = ws.pa[q], c = ws.pb[q];
+                if (kSkip && max(ws.blk[a], ws.blk[c]) >= nbv) continue;  // uniform
                 acc[q][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fh[a], fh[c], acc[q][0], 0, 0, 0);
                 acc[q][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fh[a], fl[c], acc[q][1], 0, 0, 0);
                 acc[q][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fl[a], fh[c], acc[q][1], 0, 0, 0);
@@ -839,7 +846,10 @@ __device__ __forceinline__ void gram_s16_body(
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int q = 0; q < ws.npair; ++q) flush(q, acc[q][0], acc[q][1], acc[q][2], sc);
+        for (int q = 0; q < ws.npair; ++q) {
+            if (kSkip && max(ws.blk[ws.pa[q]], ws.blk[ws.pb[q]]) >= nbv) continue;  // uniform
+            flush(q, acc[q][0], acc[q][1], acc[q][2], sc);
+        }
     };
     // all block pairs of the wave on the tile in LDS buffer b
     auto mfma_tile = [&](int b) {
@@ -866,7 +876,7 @@ __device__ __forceinline__ void gram_s16_body(
         asm volatile("" : "+v"(lo));
 #pragma unroll
         for (int q = 0; q < NPW; ++q) {
-            if (!act[q]) continue;
+            if (!act[q] || (kSkip && max(bi[q], bj[q]) >= nbv)) continue;  // uniform
             i4v_t hh = {0, 0, 0, 0}, mm = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
