@@ -15,6 +15,8 @@ does.  A missing library raises immediately: there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
 import math
 import os
 from dataclasses import dataclass
@@ -651,13 +653,82 @@ class BatchCompressor:
             self.handle = None
 
 
+_lib_id = None
+
+
+def _library_id() -> str:
+    """sha256 of the library file: tunings are kept per build."""
+    global _lib_id
+    if _lib_id is None:
+        try:
+            with open(LIB_PATH, "rb") as f:
+                _lib_id = hashlib.sha256(f.read()).hexdigest()
+        except OSError:
+            _lib_id = "missing"
+    return _lib_id
+
+
+def batch_tuning_key(shapes, dtype, eps, options, candidates_gram, candidates_ttm,
+                     device_name, library_id) -> str:
+    """Cache key of a batch tuning: everything the search depends on."""
+    blob = json.dumps({"shapes": [list(map(int, sh)) for sh in shapes], "dtype": str(dtype),
+                       "eps": float(eps), "options": options,
+                       "candidates": [list(candidates_gram), list(candidates_ttm)],
+                       "device": device_name, "library": library_id}, sort_keys=True)
+    return hashlib.sha256(blob.encode()).hexdigest()
+
+
+def load_batch_tuning(path: str, key: str):
+    """(gram_tiles_per_wg, ttm_blocks_per_wg, ms) stored under key, or None."""
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    return list(rec["gram"]), list(rec["ttm"]), float(rec["ms"])
+
+
+def store_batch_tuning(path: str, key: str, gram, ttm, ms: float) -> None:
+    """Adds key -> tuning to the JSON file at path (written whole, then renamed)."""
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        table = {}
+    table[key] = {"gram": [int(v) for v in gram], "ttm": [int(v) for v in ttm], "ms": float(ms)}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def autotune_batch(xs, eps, candidates_gram=(8, 16, 32, 64), candidates_ttm=(16, 64, 256),
-                   reps: int = 5, **kw):
+                   reps: int = 5, cache: Optional[str] = None, info: Optional[dict] = None,
+                   **kw):
     """Project autotuner for the batched path: per mode step, picks the Gram
     tiles-per-workgroup and TTM blocks-per-workgroup that minimise the time of
     a whole batch run (coordinate search, graph replays timed with events).
-    Returns (gram_tiles_per_wg, ttm_blocks_per_wg) for BatchCompressor."""
+    Returns (gram_tiles_per_wg, ttm_blocks_per_wg, ms) for BatchCompressor.
+    ``cache``: a JSON file of earlier results, keyed by the problems' shapes,
+    dtype, eps, options, candidate sets, device and library build; a hit
+    returns the stored tuning without timing anything.  ``info`` (a dict), if
+    given, receives ``cache_hit`` and ``key``."""
     n = xs[0].dim()
+    key = None
+    if cache is not None:
+        dev = xs[0].device
+        name = torch.cuda.get_device_name(dev) if dev.type == "cuda" else str(dev)
+        options = {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in kw.items()}
+        key = batch_tuning_key([x.shape for x in xs], xs[0].dtype, eps, options,
+                               candidates_gram, candidates_ttm, name, _library_id())
+        hit = load_batch_tuning(cache, key)
+        if info is not None:
+            info.update(cache_hit=hit is not None, key=key)
+        if hit is not None:
+            return hit
     g = [16] * n
     t = [64] * n
 
@@ -692,4 +763,6 @@ def autotune_batch(xs, eps, candidates_gram=(8, 16, 32, 64), candidates_ttm=(16,
             ms = timed(g, trial)
             if ms < best:
                 best, t = ms, trial
+    if cache is not None:
+        store_batch_tuning(cache, key, g, t, best)
     return g, t, best
