@@ -34,6 +34,11 @@ struct GramLaunch {
     int jb, ntasks, total_wg;
     size_t off;  // byte offset of its tasks in the table area
     bool f64;    // FP64 Gram (extents up to 32), else the split Gram
+    // split Gram loader variants to launch (launch_gram_split_batched): at the
+    // first step the strides are the input's, so L == 1 (bit 0) or not (bits
+    // 1 and 2, both, the alignment rule being the device's) is known; later
+    // strides come from ranks found on the device, and all three run
+    unsigned loaders = 7;
 };
 
 // Extent classes whose Gram runs in FP64 arithmetic: at J <= 32 the FP64
@@ -232,6 +237,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         StepPlan& sp = steps[s];
         // Gram tasks, grouped by padded-extent class
         std::map<int, std::vector<BatchGramTask>> gclass;
+        std::map<int, unsigned> gloaders;
         std::map<int, std::vector<BatchTtmTask>> tclass;
         std::map<int, int> tkmax;
         std::vector<BatchReduceTask> red;
@@ -258,6 +264,9 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
                              bufs[b].nparts, ceil_div(ntiles, nwg)};
             gt.v.nwg = nwg;
             gclass[jb].push_back(gt);
+            // the first step's view is the input's (capacities start at the
+            // extents), so its stride is exact here
+            gloaders[jb] |= s > 0 ? 7u : v.L == 1 ? 1u : 6u;
             const bool f64 = f64_class(jb);
             BatchReduceTask rt{bufs[b].partial, bufs[b].S,
                                s == 0 && h ? h->norm2_dev + b : nullptr,
@@ -309,7 +318,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             }
             sp.grams.push_back({kv.first, (int)kv.second.size(), wg,
                                 put(kv.second.data(), kv.second.size() * sizeof(BatchGramTask)),
-                                f64_class(kv.first)});
+                                f64_class(kv.first), gloaders[kv.first]});
         }
         sp.red_off = put(red.data(), red.size() * sizeof(BatchReduceTask));
         sp.red_ntasks = (int)red.size();
@@ -435,7 +444,8 @@ int sthosvd_batch_run(tk_batch* h, void* stream) {
             if (g.f64) {
                 TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 0, st));
             } else {
-                TK_TRY(launch_gram_split_batched(tasks, g.ntasks, g.total_wg, g.jb, st));
+                TK_TRY(launch_gram_split_batched(tasks, g.ntasks, g.total_wg, g.jb, g.loaders,
+                                                 st));
                 if (h->guarded && s > 0)
                     TK_TRY(launch_gram_f64_batched(tasks, g.ntasks, g.total_wg, g.jb, 2, st));
                 split = true;

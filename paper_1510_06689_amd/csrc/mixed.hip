@@ -1187,11 +1187,16 @@ int mx_gram_kt(int jb) {
 
 template <int JB>
 static int launch_split_batched_t(const BatchGramTask* tasks, int ntasks, int total_wg,
-                                  hipStream_t st) {
+                                  unsigned loaders, hipStream_t st) {
     static_assert(mx_gram_shape<JB>().G == 1, "batches need a single pair group");
+    static_assert(kUnit == 0 && kContig == 1 && kStrided == 2, "bit i of loaders is variant i");
     const size_t lds = 2 * s16_buf_bytes<JB, mx_gram_shape<JB>().KT>();
-    for (const auto fn : {gram_s16_batched<JB, kUnit>, gram_s16_batched<JB, kContig>,
-                          gram_s16_batched<JB, kStrided>}) {
+    const decltype(&gram_s16_batched<JB, kUnit>) fns[3] = {
+        gram_s16_batched<JB, kUnit>, gram_s16_batched<JB, kContig>,
+        gram_s16_batched<JB, kStrided>};
+    for (int i = 0; i < 3; ++i) {
+        if (!((loaders >> i) & 1u)) continue;
+        const auto fn = fns[i];
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
         hipLaunchKernelGGL(fn, dim3(total_wg), dim3(kMxThreads), lds, st, tasks, ntasks);
@@ -1201,11 +1206,11 @@ static int launch_split_batched_t(const BatchGramTask* tasks, int ntasks, int to
 }
 
 int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
-                              hipStream_t st) {
+                              unsigned loaders, hipStream_t st) {
     switch (jb) {
-        case 32: return launch_split_batched_t<32>(tasks_dev, ntasks, total_wg, st);
-        case 64: return launch_split_batched_t<64>(tasks_dev, ntasks, total_wg, st);
-        case 128: return launch_split_batched_t<128>(tasks_dev, ntasks, total_wg, st);
+        case 32: return launch_split_batched_t<32>(tasks_dev, ntasks, total_wg, loaders, st);
+        case 64: return launch_split_batched_t<64>(tasks_dev, ntasks, total_wg, loaders, st);
+        case 128: return launch_split_batched_t<128>(tasks_dev, ntasks, total_wg, loaders, st);
         default: return fail(TK_ERR_UNSUPPORTED, "batched split Gram: extent class %d", jb);
     }
 }

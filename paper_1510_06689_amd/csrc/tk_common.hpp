@@ -413,8 +413,11 @@ struct BatchReduceTask {
     const int* nparts;
 };
 
+// loaders: bit 0 launches the L == 1 variant, bit 1 the L % 8 == 0 one,
+// bit 2 the strided one (7: all three, when the strides are decided on the
+// device); a task whose variant is not launched gets no Gram.
 int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,
-                              hipStream_t st);
+                              unsigned loaders, hipStream_t st);
 // Sets status bit 8 of every task's problem whose FP64 Gram (2 K J^2 flops at
 // the actual shape) is at most max_flops: the split Gram skips it, the FP64
 // Gram launched with conditional = 2 takes it, and the reduction and the
