@@ -64,7 +64,7 @@ int gram_wgs(int64_t ntiles, int tpw, int jb) {
 // eigensolver launches as the others, so the step keeps one eigensolver pass.
 constexpr double kBatchF64Flops = 6e7;
 struct TtmLaunch {
-    int J, kmax, ntasks, total_wg;
+    int J, kmax, ntasks, total_wg;  // J: the largest extent of the launch's tasks
     size_t off;
 };
 struct StepPlan {
@@ -239,7 +239,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
         std::map<int, std::vector<BatchGramTask>> gclass;
         std::map<int, unsigned> gloaders;
         std::map<int, std::vector<BatchTtmTask>> tclass;
-        std::map<int, int> tkmax;
+        std::map<int, int> tkmax, tjmax;
         std::vector<BatchReduceTask> red;
         std::vector<EigArgs> eig(B);
         int red_wg = 0;
@@ -308,6 +308,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int jcls = v.J <= 32 ? 32 : v.J <= 64 ? 64 : 128;
             tclass[jcls].push_back(tt);
             tkmax[jcls] = std::max(tkmax[jcls], ea.max_rank);
+            tjmax[jcls] = std::max(tjmax[jcls], v.J);  // a mode's extent is not truncated before it
             capcur[b][n] = cap_of(sh, opt, n);
         }
         for (auto& kv : gclass) {
@@ -330,7 +331,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
                 t.v.wg_begin = wg;
                 wg += t.v.nwg;
             }
-            sp.ttms.push_back({kv.first, tkmax[kv.first], (int)kv.second.size(), wg,
+            sp.ttms.push_back({tjmax[kv.first], tkmax[kv.first], (int)kv.second.size(), wg,
                                put(kv.second.data(), kv.second.size() * sizeof(BatchTtmTask))});
         }
         done |= 1 << n;

@@ -1401,6 +1401,7 @@ static int mt_dispatch(const float* y, const ModeView& v, const double* m, int64
     const int nks = (v.J + 31) / 32;
     if (nks <= 1) return mt_pick_kb<1, X3>(y, v, m, ldm, K, transpose, z, st);
     if (nks <= 2) return mt_pick_kb<2, X3>(y, v, m, ldm, K, transpose, z, st);
+    if (nks <= 3) return mt_pick_kb<3, X3>(y, v, m, ldm, K, transpose, z, st);
     if (nks <= 4) return mt_pick_kb<4, X3>(y, v, m, ldm, K, transpose, z, st);
     if (nks <= 8) return mt_pick_kb<8, X3>(y, v, m, ldm, K, transpose, z, st);
     if (nks <= 16) return mt_pick_kb<16, X3>(y, v, m, ldm, K, transpose, z, st);
@@ -1449,9 +1450,9 @@ static int ttm_batched_nks(const BatchTtmTask* tasks, int ntasks, int total_wg, 
 #define TK_TTM_B(KB, KS)                                                            \
     if (nkb <= KB && nks <= KS)                                                     \
         return launch_ttm_batched_t<KB, KS, X3>(tasks, ntasks, total_wg, kmax, st)
-    TK_TTM_B(1, 1); TK_TTM_B(1, 2); TK_TTM_B(1, 4);
-    TK_TTM_B(2, 1); TK_TTM_B(2, 2); TK_TTM_B(2, 4);
-    TK_TTM_B(4, 1); TK_TTM_B(4, 2); TK_TTM_B(4, 4);
+    TK_TTM_B(1, 1); TK_TTM_B(1, 2); TK_TTM_B(1, 3); TK_TTM_B(1, 4);
+    TK_TTM_B(2, 1); TK_TTM_B(2, 2); TK_TTM_B(2, 3); TK_TTM_B(2, 4);
+    TK_TTM_B(4, 1); TK_TTM_B(4, 2); TK_TTM_B(4, 3); TK_TTM_B(4, 4);
 #undef TK_TTM_B
     return fail(TK_ERR_UNSUPPORTED, "batched TTM: no tile");
 }

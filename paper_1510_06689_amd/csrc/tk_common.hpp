@@ -424,6 +424,8 @@ int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int to
 // eigensolver treat it as an FP64 Gram (the eigensolver clears the bit).
 int launch_batch_mark_fp64(const BatchGramTask* tasks_dev, int ntasks, double max_flops,
                            hipStream_t st);
+// J: the largest extent among the tasks (it sets the 32-row k-steps);
+// kmax: the largest rank capacity (it sets the 16-row blocks and groups).
 int launch_ttm_bf16_batched(const BatchTtmTask* tasks_dev, int ntasks, int total_wg, int J,
                             int kmax, int precision, hipStream_t st);
 // conditional = 1: only problems whose status has bit 4 set take part (the
