@@ -48,7 +48,7 @@ constexpr int kGramLdsDoubles = 2 * JB * (KT + 1) > kGramWaves * NPW * 256
 // every KS-th k-step.  The waves form kGramWaves / KS groups of NPW pairs.
 // One workgroup's share: tiles [t0, t1) of pair group g0 .. g0 + npg - 1;
 // writes npairs * 256 partial sums at `out` (those of its own pairs).
-template <typename T, int JB, int KT, int NPW, int KS>
+template <typename T, int JB, int KT, int NPW, int KS, bool SKIP = false>
 __device__ __forceinline__ void gram_f64_body(const T* __restrict__ y, const TileMap& tm, int nb,
                                               int g0, int npg, int64_t t0, int64_t t1,
                                               double* __restrict__ out, double* lds) {
@@ -60,12 +60,17 @@ __device__ __forceinline__ void gram_f64_body(const T* __restrict__ y, const Til
     for (int e = tid; e < 2 * JB * P; e += kGramThreads) lds[e] = 0.0;
 
     const int grp = wave % NG, slice = wave / NG;
+    // SKIP (batches, J below the extent class): pairs with a block at or past
+    // ceil(J / 16) sum zeros only and skip their products (partials stay 0)
+    const int nbv = SKIP ? __builtin_amdgcn_readfirstlane((tm.J + 15) >> 4) : nb;
     int aoff[NPW], boff[NPW];
+    bool live[NPW];
 #pragma unroll
     for (int q = 0; q < NPW; ++q) {
         int p = g0 + min(grp * NPW + q, npg - 1);  // spare slots repeat the last pair
         int bi, bj;
         pair_of(p, nb, bi, bj);
+        live[q] = !SKIP || max(bi, bj) < nbv;
         aoff[q] = (bi * 16 + r16) * P + k4;
         boff[q] = (bj * 16 + r16) * P + k4;
     }
@@ -94,8 +99,10 @@ __device__ __forceinline__ void gram_f64_body(const T* __restrict__ y, const Til
                 b[q] = cur[boff[q] + ks * 4];
             }
 #pragma unroll
-            for (int q = 0; q < NPW; ++q)
+            for (int q = 0; q < NPW; ++q) {
+                if (SKIP && !live[q]) continue;  // uniform
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
+            }
         }
         if (more) ld.store(nxt);
         __syncthreads();
@@ -609,8 +616,8 @@ __global__ __launch_bounds__(kGramThreads) void gram_f64_batched(
     if (w >= active) return;  // uniform over the workgroup
     const int64_t t0 = tm.ntiles * (int64_t)w / active;
     const int64_t t1 = tm.ntiles * (int64_t)(w + 1) / active;
-    gram_f64_body<float, JB, gs.KT, gs.NPW, gs.KS>(tk.y, tm, nb, 0, npairs, t0, t1,
-                                                   tk.partial + (int64_t)w * npairs * 256, lds);
+    gram_f64_body<float, JB, gs.KT, gs.NPW, gs.KS, true>(
+        tk.y, tm, nb, 0, npairs, t0, t1, tk.partial + (int64_t)w * npairs * 256, lds);
 }
 
 template <int JB>
