@@ -49,9 +49,23 @@ bool f64_class(int jb) { return jb <= 32; }
 // Workgroups of one problem's Gram: its tiles over tiles-per-workgroup.  An
 // FP64 class's problems are small and its kernel walks finer tiles, so it
 // takes a quarter of the tiles per workgroup (more workgroups in flight).
-int gram_wgs(int64_t ntiles, int tpw, int jb) {
+int gram_wgs(int64_t ntiles, int tpw, int jb, int cap) {
     const int t = f64_class(jb) ? std::max(1, tpw / 4) : tpw;
-    return std::max(1, std::min(4096, (int)((ntiles + t - 1) / t)));
+    return std::max(1, std::min(cap, (int)((ntiles + t - 1) / t)));
+}
+
+// Workgroups per task and launch at step s of a batch of B problems.  From
+// the second step on a task's shape is known only on the device, so its
+// workgroups are counted at the capacity shape, most of which truncation
+// usually removes (the surplus exits at once, at a few microseconds per
+// thousand workgroups).  The cap, 16384 over the batch and at least 256 per
+// task, binds where that count runs far past what fills the GPU (the last
+// modes of many small problems); should the ranks come out at capacity, the
+// workgroups walk more tiles or column blocks each.  A cap of 4096 over the
+// batch also bound the middle modes' split Grams, whose truncated shapes
+// still hold real work, and slowed them.
+int batch_wg_cap(int s, int B) {
+    return s == 0 ? 4096 : std::min(4096, std::max(256, 16384 / std::max(1, B)));
 }
 
 // From the second step on, a problem of a split class whose FP64 Gram takes
@@ -195,7 +209,8 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int nb16 = 2 * (jb / 32), np16 = nb16 * (nb16 + 1) / 2;
             const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
                                                                : kDefaultGramTilesPerWg;
-            const int nwg = gram_wgs(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw, jb);
+            const int nwg = gram_wgs(make_tiles(v, mx_gram_kt(jb)).ntiles, tpw, jb,
+                                     batch_wg_cap(s, B));
             pb = std::max(pb, (size_t)nwg * np16 * 256 * sizeof(double));
             ab = std::max(ab, (size_t)nwg * 2 * sizeof(double));
             jmax = std::max(jmax, v.J);
@@ -251,7 +266,7 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int tpw = tn && tn->gram_tiles_per_wg[s] > 0 ? tn->gram_tiles_per_wg[s]
                                                                : kDefaultGramTilesPerWg;
             const int64_t ntiles = make_tiles(v, mx_gram_kt(jb)).ntiles;
-            const int nwg = gram_wgs(ntiles, tpw, jb);
+            const int nwg = gram_wgs(ntiles, tpw, jb, batch_wg_cap(s, B));
             BatchView bv{};
             for (int k = 0; k < N; ++k) bv.dims[k] = sh.dims[k];
             bv.ranks = h ? h->ranks_dev + (size_t)b * N : nullptr;
@@ -304,7 +319,8 @@ size_t plan_batch(int B, const tk_shape* shapes, const tk_options* opt, const tk
             const int bpw = tn && tn->ttm_blocks_per_wg[s] > 0 ? tn->ttm_blocks_per_wg[s]
                                                                : kDefaultTtmBlocksPerWg;
             BatchTtmTask tt{bv, (const float*)yin, ea.u, (float*)yout};
-            tt.v.nwg = std::max(1, std::min(4096, ceil_div(ceil_div(v.L * v.B, 16), bpw)));
+            tt.v.nwg = std::max(1, std::min(batch_wg_cap(s, B),
+                                            ceil_div(ceil_div(v.L * v.B, 16), bpw)));
             const int jcls = v.J <= 32 ? 32 : v.J <= 64 ? 64 : 128;
             tclass[jcls].push_back(tt);
             tkmax[jcls] = std::max(tkmax[jcls], ea.max_rank);
