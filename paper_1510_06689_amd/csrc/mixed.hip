@@ -84,9 +84,10 @@ __device__ __forceinline__ unsigned dpp_max(unsigned v) {
 //   kUnit    (L == 1): wave w owns rows [w RW, w RW + RW); lane l holds row
 //            l % RW, groups l / RW + m (64 / RW).  A load instruction reads
 //            RW consecutive rows (contiguous) of 64 / RW columns.
-//   kContig  (L % 8 == 0, 16-byte aligned): lane group of KT / 8 consecutive
+//   kContig  (L % 4 == 0, 16-byte aligned): lane group of KT / 8 consecutive
 //            threads owns one row, thread t the column group t % (KT / 8);
-//            each group is two 16-byte loads.
+//            each group is two 16-byte loads, one per 4-column half (each
+//            half lies in one run of L).
 //   kStrided (otherwise): as kContig, one element per load.
 //   kUnit4   (L == 1, J % 4 == 0, 16-byte aligned; JB >= 128): wave w owns
 //            rows [w JB/NW, (w+1) JB/NW); lane l holds the four consecutive
@@ -121,9 +122,13 @@ struct SplitTile {
     unsigned okm[NBUF];       // kUnit4: bit 8 s + e set if set s, element e is inside the tile
     int i0, cg0;
     bool owner;      // kUnit: this wave holds rows
-    // Offsets of the thread's 8 columns inside a tile.  kContig (L % 8 == 0)
-    // keeps coff[0] only: the 8 columns lie in one run of L, at coff[0] + e.
+    // Offsets of the thread's 8 columns inside a tile.  kContig (L % 4 == 0)
+    // keeps coff[0] and coff[4] only: each 4-column half lies in one run of
+    // L, at coff[0] + e and coff[4] + e - 4.  With two register tiles
+    // (L % 8 == 0 only) the second half is at coff[0] + 4 and coff[4] is not
+    // kept.
     int coff[8];
+    __device__ __forceinline__ int coff4() const { return NBUF == 2 ? coff[0] + 4 : coff[4]; }
     // Representation error of the split: per row of the thread, the sum of
     // d^2 over its elements, d = x - 2^(E-7) (hi + lo) exactly, and the
     // largest row exponent E it used.
@@ -155,7 +160,8 @@ struct SplitTile {
             cg0 = tid % NCG;
             i0 = tid / NCG;
 #pragma unroll
-            for (int e = 0; e < (MODE == kContig ? 1 : 8); ++e)
+            for (int e = 0; e < (MODE == kContig && NBUF == 2 ? 1 : 8);
+                 e += MODE == kContig ? 4 : 1)
                 coff[e] = (int)col_offset(8 * cg0 + e, tm.L, tm.J);
         }
     }
@@ -192,8 +198,9 @@ struct SplitTile {
             }
     }
 
-    // kContig, full tile (KT columns, J == JB): the elements load() reads,
-    // as raw buffer loads with no test around them.  The tile's base goes into
+    // kContig with L % 8 == 0 (the group's 8 columns in one run: its second
+    // half at coff[0] + 4), full tile (KT columns, J == JB): the elements
+    // load() reads, as raw buffer loads with no test around them.  The tile's base goes into
     // a scalar descriptor whose range is the tile, the lane's offset (row i0,
     // column 8 cg0) is fixed and the row step is a scalar offset, so no vector
     // register is written to address the loads.  The caller guarantees that
@@ -284,8 +291,8 @@ struct SplitTile {
                 const int i = row_of(m);
                 const int64_t rowbase = t.base + (int64_t)i * tm.L;
                 if (MODE == kContig && i < J && 8 * cg0 + 8 <= t.ncols) {
-                    const f4_t* p = (const f4_t*)(y + rowbase + coff[0]);
-                    const f4_t a = p[0], b = p[1];
+                    const f4_t a = *(const f4_t*)(y + rowbase + coff[0]);
+                    const f4_t b = *(const f4_t*)(y + rowbase + coff4());
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         v[m][e] = a[e];
@@ -295,7 +302,9 @@ struct SplitTile {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int kk = 8 * cg0 + e;
-                        const int ce = MODE == kContig ? coff[0] + e : coff[e];
+                        const int ce = MODE != kContig ? coff[e]
+                                       : e < 4          ? coff[0] + e
+                                                        : coff4() + e - 4;
                         v[m][e] = (i < J && kk < t.ncols) ? y[rowbase + ce] : 0.f;
                     }
                 }
@@ -1120,15 +1129,16 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
         }
     }
     if (v.L == 1) return mx_launch<JB, kUnit>(y, tm, pl, partial, st);
-    const bool contig = v.L % 8 == 0 && ((uintptr_t)y & 15) == 0;
+    const bool contig = v.L % 4 == 0 && ((uintptr_t)y & 15) == 0;
     if constexpr (JB == 128) {
-        // two register tiles: J == JB, every tile but the tensor's last full
+        // two register tiles: L % 8 == 0, J == JB, every tile but the tensor's last full
         // (KT a multiple of L when tiles pack whole b-blocks, L a multiple of
         // KT when they cut one), and a full tile spans < 2^31 bytes
         const int64_t kl = pl.KT - 1;
         const int64_t span = (int64_t)(v.J - 1) * v.L + (kl / v.L) * v.J * v.L + kl % v.L + 1;
         const bool even = tm.packed ? pl.KT % v.L == 0 : v.L % pl.KT == 0;
-        if (contig && v.J == JB && even && span * (int64_t)sizeof(float) < (int64_t(1) << 31))
+        if (contig && v.L % 8 == 0 && v.J == JB && even &&
+            span * (int64_t)sizeof(float) < (int64_t(1) << 31))
             return mx_launch<JB, kContig, 2>(y, tm, pl, partial, st);
     }
     if (contig) return mx_launch<JB, kContig>(y, tm, pl, partial, st);
@@ -1137,12 +1147,12 @@ static int mx_dispatch_mode(const float* y, const ModeView& v, const GramPlan& p
 
 // ---- batches: three launches cover every problem of a batch -------------
 // A problem's unfolding stride L depends on ranks found on the device, so
-// the three loader variants (L == 1; L % 8 == 0 with 16-byte alignment; any
+// the three loader variants (L == 1; L % 4 == 0 with 16-byte alignment; any
 // other) run over the same task table, each returning at once for the tasks
 // of the others (one variant per kernel keeps each kernel's registers those
 // of its own loader).
 __device__ __forceinline__ int batch_loader(const ModeView& mv, const float* y) {
-    return mv.L == 1 ? kUnit : (mv.L % 8 == 0 && ((uintptr_t)y & 15) == 0) ? kContig : kStrided;
+    return mv.L == 1 ? kUnit : (mv.L % 4 == 0 && ((uintptr_t)y & 15) == 0) ? kContig : kStrided;
 }
 
 template <int JB, int MODE>

@@ -413,7 +413,7 @@ struct BatchReduceTask {
     const int* nparts;
 };
 
-// loaders: bit 0 launches the L == 1 variant, bit 1 the L % 8 == 0 one,
+// loaders: bit 0 launches the L == 1 variant, bit 1 the L % 4 == 0 one,
 // bit 2 the strided one (7: all three, when the strides are decided on the
 // device); a task whose variant is not launched gets no Gram.
 int launch_gram_split_batched(const BatchGramTask* tasks_dev, int ntasks, int total_wg, int jb,

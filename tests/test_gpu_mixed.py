@@ -68,6 +68,11 @@ GRAM_CASES = [
     ((256, 128, 5), (1,)),      # each b-block cut into two full tiles
     ((24, 128, 20), (1,)),      # 128 % 24 != 0: one register tile
     ((200, 128, 3), (1,)),      # 200 % 128 != 0: one register tile
+    # L % 4 == 0, L % 8 != 0: the two 4-column halves at their own offsets
+    ((12, 40, 30), (1,)),       # packed tiles (10 b-blocks), class 64
+    ((20, 100, 9), (1,)),       # packed tiles (6 b-blocks, ragged), class 128
+    ((36, 128, 5), (1,)),       # J == 128: one register tile (two need L % 8 == 0)
+    ((132, 24, 7), (1,)),       # cut tiles (132 > 128 columns per run)
 ]
 
 
