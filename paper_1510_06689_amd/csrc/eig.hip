@@ -1010,8 +1010,8 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
     // wave 0 with the working vector in registers and the others in LDS;
     // cluster starts are found in one pass over the eigenvalues.
     const int nslot = (J + 63) / 64;
-    // per-lane slots of a vector: JP / 64 on the register path (at least 1)
-    constexpr int kGsSlots = JP > 0 ? (JP >= 64 ? JP / 64 : 1) : kMaxVecSlots;
+    // per-lane slots of a vector: JP / 64 rounded up on the register path
+    constexpr int kGsSlots = JP > 0 ? (JP + 63) / 64 : kMaxVecSlots;
     const double ortol = 1e-3 * tnorm;
     const bool clustered =
         __syncthreads_or(tid >= 1 && tid < R && lam[tid - 1] - lam[tid] <= ortol);
@@ -1344,17 +1344,23 @@ static size_t eig_region_doubles_jp(int J, int JP) {
     return r < hs ? hs : r;
 }
 
+// Register layouts: 32, 64, 96 and 128 rows (8 lanes per row, 8 columns
+// per register block); larger extents take the global-memory path (0).
+static int eig_jp(int J) { return J <= 32 ? 32 : J <= 64 ? 64 : J <= 96 ? 96 : J <= 128 ? 128 : 0; }
+
 size_t eig_lds_bytes(int J) {
-    const int JP = J <= 32 ? 32 : J <= 64 ? 64 : J <= 128 ? 128 : 0;
+    const int JP = eig_jp(J);
     return ((size_t)eig_region_doubles_jp(J, JP) + eig_small_doubles(J)) * sizeof(double);
 }
 
 int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditional,
                        int mode_bit, hipStream_t st) {
     if (jmax > 128) return fail(TK_ERR_UNSUPPORTED, "batched eigensolver: extent %d > 128", jmax);
-    // every problem uses the J = 128 register layout's launch shape; the LDS
-    // partition follows each problem's own J (region computed per J <= jmax)
-    const int region = (int)eig_region_doubles_jp(jmax, 128);
+    // every problem uses the register layout of the largest extent (96 rows
+    // up to 96, else 128); the LDS partition follows each problem's own J
+    // (region computed per J <= jmax)
+    const int jp = jmax <= 96 ? 96 : 128;
+    const int region = (int)eig_region_doubles_jp(jmax, jp);
     const size_t lds = ((size_t)region + eig_small_doubles(jmax)) * sizeof(double);
     auto launch = [&](auto fn) -> int {
         TK_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1364,12 +1370,12 @@ int launch_eig_batched(const EigArgs* args_dev, int count, int jmax, int conditi
         TK_HIP(hipGetLastError());
         return TK_OK;
     };
-    TK_TRY(launch(eig_batched<128, 1>));
+    TK_TRY(jp == 96 ? launch(eig_batched<96, 1>) : launch(eig_batched<128, 1>));
     const int nq = (jmax + kBatchGroups - 1) / kBatchGroups;
     hipLaunchKernelGGL(eig_multisect_batched, dim3(count * nq), dim3(64),
                        (size_t)2 * jmax * sizeof(double), st, args_dev, nq, conditional);
     TK_HIP(hipGetLastError());
-    return launch(eig_batched<128, 3>);
+    return jp == 96 ? launch(eig_batched<96, 3>) : launch(eig_batched<128, 3>);
 }
 
 // Extents of at least kSplitEig take three launches (reduction, multisection
@@ -1397,12 +1403,13 @@ static int launch_eig_jp(const EigArgs& a, int region, size_t lds, hipStream_t s
 }
 
 int launch_eig(const EigArgs& a, hipStream_t st) {
-    const int JP = a.J <= 32 ? 32 : a.J <= 64 ? 64 : a.J <= 128 ? 128 : 0;
+    const int JP = eig_jp(a.J);
     const int region = (int)eig_region_doubles_jp(a.J, JP);
     const size_t lds = ((size_t)region + eig_small_doubles(a.J)) * sizeof(double);
     switch (JP) {
         case 32: return launch_eig_jp<32>(a, region, lds, st);
         case 64: return launch_eig_jp<64>(a, region, lds, st);
+        case 96: return launch_eig_jp<96>(a, region, lds, st);
         case 128: return launch_eig_jp<128>(a, region, lds, st);
         default: return launch_eig_jp<0>(a, region, lds, st);
     }

@@ -277,6 +277,12 @@ STHOSVD_CASES = [
     ((1, 30, 9), (1, 4, 3), 0.8, 1e-3, None, None),               # extent-1 mode
     ((50,), (5,), 1.0, 1e-2, None, None),                         # N = 1
     ((130, 70), (10, 10), 0.5, 1e-5, None, None),                 # N = 2, ragged blocks
+    # the 96-row register layout (64 < J <= 96): its largest and smallest
+    # extents, and every vector of a full-rank J = 80 spectrum (eps = 0; the
+    # noise eigenvalues form one cluster)
+    ((96, 20, 10), (12, 6, 4), 0.8, 1e-4, None, None),
+    ((65, 24, 9), (9, 5, 3), 0.7, 1e-3, None, None),
+    ((80, 40, 30), (20, 8, 6), 0.9, 0.0, None, None),
     ((8, 8, 8, 8, 8), (2, 3, 2, 3, 2), 0.9, 1e-3, (4, 3, 2, 1, 0), None),
     # extents above 128: the tridiagonal reduction runs in global memory for
     # J - 128 columns (in panels of eight, the last one partial) before the
