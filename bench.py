@@ -785,7 +785,8 @@ def main():
     if x32 is not None:
         peaks = observed_peaks(x32)
         if head == "mixed":
-            peaks["roofline_achieved_over_read"] = round(roof["achieved"] / peaks["hbm_read_gbs"], 4)
+            peaks["roofline_achieved_over_read"] = round(
+                roof["achieved"] / peaks["hbm_read_gbs"], 4)
         out["observed_peaks"] = peaks
         log(f"[peaks] {peaks}")
     if x32 is not None and not args.no_cpu_baseline:
