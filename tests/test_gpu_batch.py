@@ -144,3 +144,33 @@ def test_batch_rejects_unsupported():
     with pytest.raises(tucker.TuckerError) as e:
         tucker.BatchCompressor([big], 1e-3)
     assert e.value.status == -2
+
+
+def test_batch_of_many_large_problems_matches_single_path():
+    """Sixteen problems of extent 80..93 from the 64-problem benchmark batch.
+    At this size and count the later steps' workgroups per task are capped
+    (the last mode's FP64 Gram, counted at the capacity shape, would take
+    about 1500 per task; the cap is max(256, 16384 / 16) = 1024), so the capped
+    partition must still give every problem the single-problem path's ranks
+    and the planted ones, within the error target."""
+    ws = synth.batch_workload()
+    pick = [i for i, w in enumerate(ws) if w.dims[0] >= 80][:16]
+    assert len(pick) == 16
+    eps = ws[0].eps
+    xd = [to_dev(ws[i].make(dtype=torch.float64).float()) for i in pick]
+    c = tucker.BatchCompressor(xd, eps)
+    c.run()
+    c.finish()
+    res = c.results()
+    for i, d, r in zip(pick, xd, res):
+        single = tucker.sthosvd(d, eps, gram_precision="split_bf16", ttm_precision="bf16x3")
+        say(f"problem {i} {tuple(d.shape)}: batch {r.ranks} single {single.ranks} "
+            f"planted {ws[i].ranks}")
+        assert r.ranks == single.ranks == tuple(ws[i].ranks)
+        rel, rel1 = _relerr(d, r), _relerr(d, single)
+        assert rel <= eps and rel1 <= eps
+        # the same truncation through both paths: at errors near the noise
+        # (1e-5 here) the split-bf16 TTM's rounding, 2^-16 relative per mode,
+        # is of the same size, so the two paths (different kernels and
+        # summation orders) may differ by up to N 2^-16
+        assert abs(rel - rel1) <= d.dim() * 2.0**-16, (rel, rel1)
