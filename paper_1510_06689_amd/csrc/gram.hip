@@ -550,17 +550,20 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const BatchReduceTask
             __syncthreads();
         }
         if (tk.nu == nullptr) return;
-        if (threadIdx.x < 64) {
-            double acc = 0.0;
-            for (int i = o; i < tk.J; i += 64) {
-                const int bi = i >> 4, p = bi * tk.nb - bi * (bi - 1) / 2;
-                const int idx = p * 256 + (i & 15) * 17;
-                double d = 0.0;
-                for (int q = 0; q < P; ++q) d += tk.partial[(int64_t)q * n + idx];
-                acc += d;
-            }
-            part[0][o] = acc;
+        // each diagonal entry summed as the other workgroups sum S's entries
+        // (four slot groups, eight loads in flight each, then added in a
+        // fixed order), the entries then lane by lane
+        double acc = 0.0;
+        for (int i0 = 0; i0 < tk.J; i0 += 64) {  // uniform
+            const int i = i0 + o;
+            const int bi = i >> 4, p = bi * tk.nb - bi * (bi - 1) / 2;
+            const int idx = p * 256 + (i & 15) * 17;
+            part[g][o] = i < tk.J ? sum_partials(tk.partial, P, n, idx, g) : 0.0;
+            __syncthreads();
+            if (g == 0) acc += ((part[0][o] + part[1][o]) + part[2][o]) + part[3][o];
+            __syncthreads();
         }
+        if (g == 0) part[0][o] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
