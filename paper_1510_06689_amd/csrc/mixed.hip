@@ -1033,8 +1033,8 @@ constexpr bool mx_int8() {
 // UNIT: the view has L == 1.  At extent 256 its loaders (one register tile)
 // leave room for 17 pairs per wave: one pair group of 136 on tiles of 128
 // columns, so every tile is split once and the FP64 flushes come once per
-// 128 columns; the strided loaders leave room for 6 (three groups of 46 on
-// tiles of 64).  A pair's int32 sums live only
+// 128 columns; the strided loaders leave room for 9 (two groups of 68 on
+// tiles of 64: three groups of 46 took a quarter longer).  A pair's int32 sums live only
 // from its first MFMA to its flush; the FP64 accumulators of all the wave's
 // pairs (8 registers each) are what limits the count.
 template <int JB, bool UNIT = false>
@@ -1043,7 +1043,7 @@ constexpr MxGramShape mx_gram_shape() {
            : JB == 64  ? MxGramShape{128, 2, 1, 2, 8}    //  10 16-pairs
            : JB == 128 ? MxGramShape{128, 5, 1, 1, 8}    //  36 16-pairs, 9 per SIMD
            : JB == 256 ? (UNIT ? MxGramShape{128, 17, 1, 1, 8}   // 136 16-pairs: 1 x 136
-                               : MxGramShape{64, 6, 3, 1, 8})    //               3 x 46
+                               : MxGramShape{64, 9, 2, 1, 8})    //               2 x 68
                        : MxGramShape{16, 2, 9, 1, 8};    // 136 32-pairs: 9 groups of 16
 }
 template <int JB>

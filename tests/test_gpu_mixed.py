@@ -73,6 +73,8 @@ GRAM_CASES = [
     ((20, 100, 9), (1,)),       # packed tiles (6 b-blocks, ragged), class 128
     ((36, 128, 5), (1,)),       # J == 128: one register tile (two need L % 8 == 0)
     ((132, 24, 7), (1,)),       # cut tiles (132 > 128 columns per run)
+    ((7, 200, 9), (1,)),        # J class 256, strided loader (L = 7), pair groups
+    ((32, 256, 40), (1,)),      # J = 256, contiguous loader (L = 32), pair groups
 ]
 
 
