@@ -577,16 +577,32 @@ __device__ __forceinline__ void eig_body(const EigArgs& a, int region) {
                 vj[q] = q < nq ? Vs[q * J + t0 + jb] : 0.0;
                 wj[q] = q < nq ? Ws[q * J + t0 + jb] : 0.0;
             }
-            for (int i = ir; i < mt; i += 4) {
-                double t = 0.0;
+            // rows in batches of UR whose loads go out together (a row's
+            // store would otherwise hold back the next row's load: the
+            // compiler cannot tell the addresses apart); each element has
+            // one owner, so the values are those of a row-by-row pass
+            constexpr int UR = 4;
+            for (int i0 = ir; i0 < mt; i0 += 4 * UR) {  // uniform over the wave
+                double av[UR];
 #pragma unroll
-                for (int q = 0; q < kPanel; ++q) {
-                    if (q < nq) {
-                        const double vi = Vs[q * J + t0 + i], wi = Ws[q * J + t0 + i];
-                        t = __dadd_rn(t, __dadd_rn(__dmul_rn(vi, wj[q]), __dmul_rn(wi, vj[q])));
-                    }
+                for (int u = 0; u < UR; ++u) {
+                    const int i = min(i0 + 4 * u, mt - 1);  // in bounds; unused past mt
+                    av[u] = A[(size_t)(t0 + i) * J + t0 + jb];
                 }
-                A[(size_t)(t0 + i) * J + t0 + jb] -= t;
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    const int i = i0 + 4 * u;
+                    if (i >= mt) break;  // uniform over the wave
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kPanel; ++q) {
+                        if (q < nq) {
+                            const double vi = Vs[q * J + t0 + i], wi = Ws[q * J + t0 + i];
+                            t = __dadd_rn(t, __dadd_rn(__dmul_rn(vi, wj[q]), __dmul_rn(wi, vj[q])));
+                        }
+                    }
+                    A[(size_t)(t0 + i) * J + t0 + jb] = av[u] - t;
+                }
             }
         }
         __syncthreads();
