@@ -432,7 +432,9 @@ typedef struct tk_batch_outputs {
 /* Work partition: column tiles per Gram workgroup and 16-column blocks per
  * TTM workgroup, per mode (0 = default).  Chosen by an autotuner in the
  * Python layer; any positive values give the same results up to summation
- * order. */
+ * order.  The values are targets: workgroups per problem are capped at 4096,
+ * and from the second mode step on (whose shapes are counted at the rank
+ * capacities) at max(256, 16384 / batch), so a workgroup may take more. */
 typedef struct tk_batch_tuning {
     int32_t gram_tiles_per_wg[TK_MAX_NDIM];
     int32_t ttm_blocks_per_wg[TK_MAX_NDIM];
